@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of the FFT + Thomas Poisson solve on one MI355X.
+
+Metric: grid points solved per second (Mpts/s) at 512^3, periodic x,y /
+Neumann z, source = discrete divergence of a seeded Gaussian velocity field
+(workload div_ppn), in double precision; the float solve wrapped in double
+iterative refinement is timed beside it.  One step = one complete solve
+(x forward transform, z march with the y transforms and z solves, x inverse
+transform, reductions) of one right-hand side already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload div_ppn]
+
+Prints one JSON line on stdout; progress goes to stderr.  The per-kernel
+durations come from HIP events the library records on the solve's stream
+during the timed steps.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpts/s per solve at 512^3 (FP64 vs FP32+refine @1e-12); % peak HBM BW"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published peak
+GROUPS = ("x_forward", "z_march", "x_inverse", "other")
+KERNEL_NAMES = {"x_forward": "k_xfwd", "z_march": "k_zmarch", "x_inverse": "k_xinv"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+SOURCES = [os.path.join(ROOT, "paper_1909_05423_amd", "csrc", n)
+           for n in ("pp_device.hpp", "pp_kernels.hpp", "xdir.hip", "zmarch.hip")]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(plan_shape, batch, slots, elem_in, elem_spec):
+    """Bytes each kernel must move through HBM per launch (one pass over its
+    input and output), as a dict keyed by kernel group."""
+    nz, ny, nx = plan_shape
+    n = nx * ny * nz * batch
+    spec = slots * ny * nz * batch * elem_spec     # spectral array S (complex)
+    return {
+        "x_forward": n * elem_in + spec,           # read f, write S
+        "z_march": 4 * spec,                       # read+write S upward, read+write S downward
+        "x_inverse": spec + n * elem_in,           # read S, write u
+    }
+
+
+def traffic_for(group, workload, dtype):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by the copy-kernel calibration), if taken on the current kernels."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    entry = data.get("entries", {}).get(f"{workload}/{dtype}/{group}")
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def time_solves(plan, f, u, steps, warmup, lib):
+    import ctypes
+    import torch
+    for _ in range(warmup):
+        plan.solve(f, u)
+    torch.cuda.synchronize()
+    lib.pp_plan_set_timing(plan._handle, 1)
+    lib.pp_plan_kernel_times(plan._handle, None, None, 1)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        plan.solve(f, u)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int * 4)()
+    lib.pp_plan_kernel_times(plan._handle, ms, cnt, 1)
+    lib.pp_plan_set_timing(plan._handle, 0)
+    per = {}
+    for g, name in enumerate(GROUPS):
+        per[name] = dict(total_ms=ms[g], launches=cnt[g], avg_ms=(ms[g] / cnt[g] if cnt[g] else None))
+    return start.elapsed_time(end) / steps, wall, per
+
+
+def roofline_block(per, abytes, workload, dtype):
+    best = None
+    for g in ("x_forward", "z_march", "x_inverse"):
+        k = per[g]
+        if k["launches"] and (best is None or k["total_ms"] > per[best]["total_ms"]):
+            best = g
+    k = per[best]
+    achieved = abytes[best] / (k["avg_ms"] * 1e-3) / 1e9
+    traffic = traffic_for(best, workload, dtype)
+    return dict(bound="hbm", kernel=KERNEL_NAMES[best], achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
+                unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                bytes_per_launch=abytes[best], avg_launch_ms=round(k["avg_ms"], 5))
+
+
+def cpu_baseline(workload_name):
+    """The oracle, timed on this host, on the same recipe at 256^3 (1/8 of the points)."""
+    import numpy as np
+    import oracle
+    import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    shape = (256, 256, 256)
+    wl = workloads.make(workload_name, shape=shape, batch=1)
+    t0 = time.perf_counter()
+    u = oracle.solve(wl["f"][0], wl["bc"], wl["h"])
+    dt = time.perf_counter() - t0
+    del u
+    pts = float(np.prod(shape))
+    return dict(value=round(pts / dt / 1e6, 3), unit="Mpts/s", cores=int(threads), kind="oracle",
+                sample=f"one oracle solve of the {workload_name} recipe at 256^3 "
+                       f"({dt:.1f} s wall, float64 numpy, BLAS threads {threads})")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="div_ppn")
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-refined", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1909_05423_amd import Plan, _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1909_05423_amd import build
+        log("library not built; building")
+        build.build()
+    lib = _lib.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+
+    log(f"generating workload {args.workload}")
+    wl = workloads.make(args.workload)
+    shape, bc, h, batch = wl["shape"], wl["bc"], wl["h"], wl["batch"]
+    npts = float(np.prod(shape)) * batch
+    f = torch.from_numpy(wl["f"]).to("cuda")
+    f_host = wl.pop("f")
+    u = torch.empty_like(f)
+
+    log(f"plan f64 {shape} {bc} batch {batch}")
+    plan = Plan(shape, bc, h, dtype="f64", batch=batch)
+    ms, wall, per = time_solves(plan, f, u, args.steps, args.warmup, lib)
+    log(f"f64: {ms:.3f} ms/solve, {npts / ms / 1e3:.0f} Mpts/s")
+    slots = (shape[2] + 1) // 2
+    ab64 = algorithmic_bytes(shape, batch, slots, 8, 16)
+    kern = {g: dict(per[g]) for g in GROUPS}
+    for g in ab64:
+        if per[g]["avg_ms"]:
+            kern[g]["algorithmic_GBs"] = round(ab64[g] / (per[g]["avg_ms"] * 1e-3) / 1e9, 1)
+    total_bytes = sum(ab64.values())
+    result = {
+        "metric": METRIC,
+        "value": round(npts / ms / 1e3, 1),
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "shape_zyx": list(shape), "bc": bc, "batch": batch,
+                   "h": list(h)},
+        "roofline": roofline_block(per, ab64, args.workload, "f64"),
+        "solve_hbm_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
+        "solve_hbm_frac": round(total_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "kernels": kern,
+    }
+
+    # correctness of the timed result (outside the timed region): normwise backward error
+    import oracle
+    u64 = u.cpu().numpy()
+    fp = f_host - f_host.mean(axis=(1, 2, 3), keepdims=True) if oracle.is_singular(bc) else f_host
+    eta = max(oracle.backward_error(fp[b], u64[b], bc, h) for b in range(batch))
+    result["f64_backward_error"] = float(eta)
+    log(f"f64 backward error {eta:.2e}")
+
+    if not args.skip_refined:
+        plan_r = Plan(shape, bc, h, dtype="f32_refined", batch=batch)
+        ur = torch.empty_like(f)
+        ms_r, _, per_r = time_solves(plan_r, f, ur, max(3, args.steps // 2), 2, lib)
+        its, _, rel = plan_r.last_info()
+        diff = float((ur - u).abs().max() / u.abs().max())
+        result["fp32_refined"] = {
+            "value": round(npts / ms_r / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_r, 4),
+            "refinement_steps": its, "last_rel_correction": rel, "max_rel_diff_vs_f64": diff,
+            "kernels": {g: dict(per_r[g]) for g in GROUPS},
+        }
+        log(f"f32+refine: {ms_r:.3f} ms/solve, {its} corrections, diff vs f64 {diff:.2e}")
+        del plan_r, ur
+
+    if not args.skip_cpu_baseline:
+        log("timing the oracle on a 256^3 sample")
+        result["cpu_baseline"] = cpu_baseline(args.workload)
+    result["context"] = {"paper_single_gpu_512cubed_Mpts_s": {"V100": 4.09, "K40": 1.56},
+                         "note": "paper's multi-GPU code path on one GPU, boundary conditions unstated"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+/*
+ * ppsolve — FFT + Thomas direct solve of the second-order 7-point Poisson
+ * problem on one AMD MI355X (gfx950).
+ *
+ * Method: PittPack, Hasbestan & Senocak, arXiv:1909.05423.  The discrete
+ * problem is the cell-centred 7-point stencil of section "Mathematical
+ * Formulation" (Eq. 3) on a directionally uniform grid, with periodic,
+ * homogeneous Dirichlet or homogeneous Neumann faces (section "Boundary
+ * Conditions").  The solve applies the forward real transforms along x and y
+ * (periodic -> DFT, Neumann -> DCT-II, Dirichlet -> DST-II; Table
+ * TransformationList), one tridiagonal solve along z per wavenumber pair with
+ * the modified wavenumbers of Table eig (section "Solution of the Resulting
+ * Tridiagonal Matrices", Algorithm Thomas for Toeplitz Matrices), and the
+ * inverse transforms.  The singular zero mode of pure Neumann/periodic problems
+ * is pinned (section "Well-posedness").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays are C-contiguous (batch, nz, ny, nx), x fastest, in device memory.
+ * Cell (i, j, k) sits at ((i + 1/2) hx, (j + 1/2) hy, (k + 1/2) hz).
+ * The equation is  sum_d (u_{+1} - 2 u + u_{-1}) / h_d^2 = f  (no minus sign).
+ * The caller owns f, u and the workspace; a plan owns only host memory.
+ * Every launch goes on the caller's HIP stream (`stream` is a hipStream_t;
+ * NULL is the default stream) and the calls return before the GPU work ends,
+ * except the refined mode, which reads one pair of scalars back per
+ * refinement step.  No status crosses the ABI as an exception.
+ */
+#ifndef PPSOLVE_H
+#define PPSOLVE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_plan_s* pp_plan;
+
+/* Arithmetic of a plan.
+ *   PP_F64          f, u are double; transforms and z-solves in double.
+ *   PP_F32          f, u are float; transforms and z-solves in float.
+ *   PP_F32_REFINED  f, u are double; every solve runs in float, wrapped in
+ *                   iterative refinement whose residual (the 7-point stencil of
+ *                   Eq. 3 with the face ghost rules) and solution update are
+ *                   accumulated in double on the GPU. */
+typedef enum { PP_F64 = 0, PP_F32 = 1, PP_F32_REFINED = 2 } pp_dtype;
+
+/* Treatment of the singular zero mode (pure Neumann/periodic x and y with
+ * Neumann on both z faces); ignored for non-singular problems.
+ *   PP_GAUGE_MEAN     subtract the volume mean of f (the alternative the
+ *                     "Well-posedness" section names), pin, then shift u to
+ *                     zero volume mean.  Unique; the solve operator is symmetric.
+ *   PP_GAUGE_PIN      subtract the mean of f and pin: the first unknown of the
+ *                     (kx, ky) = (0, 0) z-system is zero, i.e. the mean of u over
+ *                     the first z plane is zero (the paper's default pin).
+ *   PP_GAUGE_PIN_RAW  pin only, no projection: the plane z = 0 absorbs the
+ *                     incompatible part of f. */
+typedef enum { PP_GAUGE_MEAN = 0, PP_GAUGE_PIN = 1, PP_GAUGE_PIN_RAW = 2 } pp_gauge;
+
+typedef enum {
+    PP_OK = 0,
+    PP_ERR_ARG = -1,           /* null pointer, non-positive size/spacing/batch, bad enum */
+    PP_ERR_BC = -2,            /* bc char not in {P,D,N}; x or y faces of different types;
+                                  periodic z (not supported) */
+    PP_ERR_SIZE = -3,          /* nx or ny has a prime factor other than 2 and 3, or exceeds
+                                  the on-chip line limit (2048), or nz * batch > 65535 */
+    PP_ERR_ALIAS = -4,         /* u (or out) overlaps f (or g) or the workspace */
+    PP_ERR_WORKSPACE = -5,     /* workspace pointer null or misaligned (256 B) */
+    PP_ERR_HIP = -6,           /* a HIP call failed (launch, copy, synchronisation) */
+    PP_ERR_NOT_CONVERGED = -7, /* refinement did not reach its tolerance in max_iter steps */
+    PP_ERR_NONFINITE = -8      /* the source held an Inf or NaN (reported where the
+                                  library reads scalars back: refinement, last_info) */
+} pp_status;
+
+/* Create a plan (host only; no GPU call).
+ *   nx, ny, nz  cells per direction, >= 1.  nx and ny must factor as 2^a 3^b.
+ *   bc          6 chars for the faces (x-, x+, y-, y+, z-, z+) from
+ *               'P' periodic, 'D' homogeneous Dirichlet (value 0 on the face,
+ *               ghost cell by linear extrapolation), 'N' homogeneous Neumann
+ *               (zero flux).  The two x faces share a type, as do the two y
+ *               faces (Table eig lists only PP, NN, DD); z faces are D or N,
+ *               each independently.
+ *   h           spacings (hx, hy, hz) > 0.
+ *   dtype       see pp_dtype.  batch: independent right-hand sides, >= 1.
+ * On success *out holds a plan to release with pp_plan_destroy.  The gauge
+ * defaults to PP_GAUGE_MEAN; refinement to tol 1e-13 (estimated relative
+ * error), max_iter 8. */
+pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double h[3],
+                         pp_dtype dtype, int batch, pp_plan* out);
+
+/* Select the zero-mode treatment (see pp_gauge). */
+pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
+
+/* Refinement controls for PP_F32_REFINED: stop once the estimated relative
+ * error of u (max-norm; the size of the next correction predicted from the
+ * last two) is at most tol, or after max_iter correction steps (max_iter = 0
+ * runs the float solve alone and reports PP_ERR_NOT_CONVERGED). */
+pp_status pp_plan_set_refinement(pp_plan p, double tol, int max_iter);
+
+/* Bytes of device workspace the caller must pass to pp_solve/pp_solve_adjoint
+ * (256-byte aligned).  0 for a null plan. */
+size_t pp_plan_workspace_bytes(pp_plan p);
+
+/* Solve L_h u = f for every batch entry.  f and u: device arrays of
+ * batch*nz*ny*nx doubles (PP_F64, PP_F32_REFINED) or floats (PP_F32); they
+ * must not overlap each other or the workspace.  The first call with a given
+ * workspace pointer uploads the plan's tables into it (an asynchronous copy on
+ * `stream`); later calls with the same pointer reuse them, so the workspace
+ * must not be modified between solves.  f is read only. */
+pp_status pp_solve(pp_plan p, const void* f, void* u, void* workspace, void* stream);
+
+/* out = G^T g, the transpose of the linear map f -> u that pp_solve applies,
+ * for dJ/df = G^T dJ/du.  Same array rules as pp_solve.  The transforms, the
+ * z-systems (symmetric: equal off-diagonals) and the per-mode weights of the
+ * real-data transforms transpose into the same stage sequence as the forward
+ * solve; what changes is the zero-mode treatment, whose projection and mean
+ * shift trade places (PP_GAUGE_PIN: pin, then subtract the mean of the
+ * result). */
+pp_status pp_solve_adjoint(pp_plan p, const void* g, void* out, void* workspace, void* stream);
+
+/* Results of the last pp_solve/pp_solve_adjoint on this plan; synchronises
+ * with that call's stream.  Any pointer may be NULL.
+ *   ir_iters          refinement corrections applied (0 unless PP_F32_REFINED)
+ *   removed_mean      array of `batch` doubles: volume mean of the source that
+ *                     the projection removed (0 where nothing was removed)
+ *   final_rel_update  last ||correction||_inf / ||u||_inf (refined mode)
+ * Returns PP_ERR_NONFINITE when the last source held an Inf or NaN. */
+pp_status pp_plan_last_info(pp_plan p, int* ir_iters, double* removed_mean, double* final_rel_update);
+
+/* Kernel timing (off by default).  With timing on, every solve records HIP
+ * events on its stream around each kernel launch.  pp_plan_kernel_times
+ * synchronises with the recorded events and returns, for the kernel groups
+ *   0 x forward (transform + transpose), 1 z march (y transforms + z solves),
+ *   2 x inverse, 3 everything else (reductions, residual, refinement control),
+ * the accumulated milliseconds and launch counts since the last reset
+ * (arrays of 4; either may be NULL); reset != 0 clears the accumulators. */
+pp_status pp_plan_set_timing(pp_plan p, int on);
+pp_status pp_plan_kernel_times(pp_plan p, double* ms, int* launches, int reset);
+
+void pp_plan_destroy(pp_plan p);
+
+/* Static, NUL-terminated description of a status code. */
+const char* pp_status_string(pp_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPSOLVE_H */

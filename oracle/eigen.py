@@ -28,4 +28,7 @@ def eigenvalues(kind, n, h):
     else:
         raise ValueError(f"unknown boundary type {kind!r}")
     num = np.mod(num, 2 * den)
-    return (-2.0 + 2.0 * np.cos(np.pi * (num.astype(np.float64) / den))) / (h * h)
+    # -2 + 2 cos(t) evaluated as -4 sin^2(t / 2): the same value without the
+    # cancellation that costs -2 + 2 cos(t) its relative accuracy for small t.
+    half_angle = 0.5 * np.pi * (num.astype(np.float64) / den)
+    return -4.0 * np.sin(half_angle) ** 2 / (h * h)

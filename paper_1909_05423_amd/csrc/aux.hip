@@ -1,0 +1,156 @@
+// Small kernels around the solve: reductions of per-workgroup partials, the
+// double-precision 7-point residual of the refinement loop and its control
+// scalars.
+
+#include <cmath>
+
+#include "pp_kernels.hpp"
+
+namespace pp {
+
+constexpr int kRedThreads = 1024;
+
+// One workgroup: per batch entry, the sum of the (sum, max) pairs written by
+// the forward x kernel, in a fixed order (deterministic).
+__global__ __launch_bounds__(kRedThreads) void k_finalize_xfwd(const double* __restrict__ partial, int nper,
+                                                               int batch, double npts, double* __restrict__ mu,
+                                                               double* __restrict__ maxf) {
+    __shared__ double red[kRedThreads / 64];
+    double gmax = 0.0;
+    for (int b = 0; b < batch; ++b) {
+        double s = 0.0, mx = 0.0;
+        for (int i = threadIdx.x; i < nper; i += kRedThreads) {
+            s += partial[2 * ((size_t)b * nper + i)];
+            mx = fmax(mx, partial[2 * ((size_t)b * nper + i) + 1]);
+        }
+        const double bs = block_sum<kRedThreads>(s, red);
+        const double bm = block_max<kRedThreads>(mx, red);
+        if (threadIdx.x == 0) {
+            mu[b] = bs / npts;
+            gmax = fmax(gmax, bm);
+        }
+    }
+    if (threadIdx.x == 0 && maxf) *maxf = gmax;
+}
+
+hipError_t launch_finalize_xfwd(const double* partial, int nper, int batch, double npts, double* mu, double* maxf,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_xfwd, dim3(1), dim3(kRedThreads), 0, s, partial, nper, batch, npts, mu, maxf);
+    return hipGetLastError();
+}
+
+// Refinement bookkeeping after an update: gauge shift per batch entry (mean of
+// u over the gauge region, removed by the next update), the size of the last
+// correction relative to u, and the power-of-two scale of the next residual so
+// that its float image stays well inside the float range.
+__global__ __launch_bounds__(kRedThreads) void k_finalize_update(const double* __restrict__ partial, int nper,
+                                                                 int batch, double nregion,
+                                                                 double* __restrict__ sc, int first) {
+    __shared__ double red[kRedThreads / 64];
+    double gd = 0.0, gu = 0.0;
+    for (int b = 0; b < batch; ++b) {
+        double s = 0.0, md = 0.0, mu = 0.0;
+        for (int i = threadIdx.x; i < nper; i += kRedThreads) {
+            const size_t k = 3 * ((size_t)b * nper + i);
+            s += partial[k];
+            md = fmax(md, partial[k + 1]);
+            mu = fmax(mu, partial[k + 2]);
+        }
+        const double bs = block_sum<kRedThreads>(s, red);
+        const double bd = block_max<kRedThreads>(md, red);
+        const double bu = block_max<kRedThreads>(mu, red);
+        if (threadIdx.x == 0) {
+            sc[SC_COUNT + 2 * batch + b] = nregion > 0.0 ? bs / nregion : 0.0;
+            gd = fmax(gd, bd);
+            gu = fmax(gu, bu);
+        }
+    }
+    if (threadIdx.x == 0) {
+        const double rel = gu > 0.0 ? gd / gu : 0.0;
+        sc[SC_RELPREV] = first ? 1.0 : sc[SC_REL];
+        sc[SC_MAXD] = gd;
+        sc[SC_MAXU] = gu;
+        sc[SC_REL] = rel;
+        const double est = sc[SC_MAXF] * (rel > 0.0 ? rel : 1.0);
+        int e = 0;
+        if (est > 0.0 && isfinite(est)) e = ilogb(est);
+        e = max(-1000, min(1000, e));
+        sc[SC_SCALE] = ldexp(1.0, -e);
+        sc[SC_INVSCALE] = ldexp(1.0, e);
+    }
+}
+
+hipError_t launch_finalize_update(const double* partial, int nper, int batch, double nregion, double* scalars,
+                                  int first, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_update, dim3(1), dim3(kRedThreads), 0, s, partial, nper, batch, nregion, scalars,
+                       first);
+    return hipGetLastError();
+}
+
+// r = scale * (f - c - L_h u) in double, stored as float (c: see ResidualArgs;
+// removing it in double keeps the float image of r at the precision of the
+// small correction it carries).  L_h: the 7-point stencil
+// of Eq. 3 with the face ghost rules (periodic wrap; Dirichlet ghost = -u of
+// the boundary cell, linear extrapolation to a zero face value; Neumann ghost
+// = u of the boundary cell).
+__device__ __forceinline__ double ghost_or(const double* p, long stride, int idx, int n, int kind_lo, int kind_hi,
+                                           int dir, double self) {
+    // neighbour at idx + dir along one axis of length n
+    const int q = idx + dir;
+    if (q >= 0 && q < n) return p[(long)dir * stride];
+    const int kind = dir < 0 ? kind_lo : kind_hi;
+    if (kind == BC_P) return p[(long)(dir < 0 ? (n - 1) : -(n - 1)) * stride];
+    return kind == BC_D ? -self : self;
+}
+
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, const double* __restrict__ u,
+                                                  float* __restrict__ r, ResidualArgs a,
+                                                  const double* __restrict__ sc) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    const int kb = blockIdx.z;
+    if (i >= a.nx || j >= a.ny) return;
+    const int k = kb % a.nz;
+    const size_t idx = (((size_t)kb) * a.ny + j) * a.nx + i;
+    const double* p = u + idx;
+    const double c = *p;
+    const double lx = ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], -1, c) + ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], 1, c);
+    const double ly = ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], -1, c) +
+                      ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], 1, c);
+    const long sz = (long)a.nx * a.ny;
+    const double lz = ghost_or(p, sz, k, a.nz, a.bc[4], a.bc[5], -1, c) + ghost_or(p, sz, k, a.nz, a.bc[4], a.bc[5], 1, c);
+    const double lap = (lx - 2.0 * c) * a.ihx2 + (ly - 2.0 * c) * a.ihy2 + (lz - 2.0 * c) * a.ihz2;
+    double fi = f[idx];
+    if (a.proj) {
+        const double mu = sc[SC_COUNT + 3 * a.batch + kb / a.nz];
+        if (a.proj == 1) fi -= mu;
+        else if (k == 0) fi -= (double)a.nz * mu;
+    }
+    r[idx] = (float)((fi - lap) * sc[SC_SCALE]);
+}
+
+hipError_t launch_residual(const double* f, const double* u, float* r, const ResidualArgs& a, const double* scalars,
+                           hipStream_t s) {
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz * a.batch);
+    hipLaunchKernelGGL(k_residual, grid, dim3(64, 4), 0, s, f, u, r, a, scalars);
+    return hipGetLastError();
+}
+
+// Set the scalars that the first (unrefined) float solve reads in update mode.
+__global__ void k_ir_init(double* sc, int batch) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        sc[SC_SCALE] = 1.0;
+        sc[SC_INVSCALE] = 1.0;
+        sc[SC_REL] = 1.0;
+        sc[SC_RELPREV] = 1.0;
+    }
+    for (int b = t; b < batch; b += blockDim.x) sc[SC_COUNT + 2 * batch + b] = 0.0;
+}
+
+hipError_t launch_ir_init(double* scalars, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_ir_init, dim3(1), dim3(64), 0, s, scalars, batch);
+    return hipGetLastError();
+}
+
+}  // namespace pp

@@ -1,0 +1,681 @@
+// Plan creation, table construction, workspace layout and the launch sequences
+// behind the C ABI of include/ppsolve.h.
+//
+// Host-side numerics (all double, angles reduced exactly over the integers and
+// evaluated in long double before rounding):
+//   * FFT twiddles exp(-2 pi i j / N) and the DCT twiddles exp(-i pi k / (2N));
+//   * the 1-D eigenvalues of Table eig, written -4 sin^2(t/2) / h^2 (equal to
+//     the table's -2 + 2 cos(t), without its cancellation at small t);
+//   * the reciprocal pivots of every z-system (section "Solution of the
+//     Resulting Tridiagonal Matrices", Algorithm Thomas for Toeplitz Matrices)
+//     up to the index where they stop changing in the solve's precision.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/ppsolve.h"
+#include "pp_kernels.hpp"
+
+using pp::cplx;
+
+struct pp_plan_s {
+    int nx = 0, ny = 0, nz = 0, batch = 0;
+    char bc[6] = {0};
+    double h[3] = {0, 0, 0};
+    pp_dtype dtype = PP_F64;
+    pp_gauge gauge = PP_GAUGE_MEAN;
+    double ir_tol = 1e-13;
+    int ir_max = 8;
+    // derived
+    int bx = 0, by = 0, bz0 = 0, bz1 = 0;
+    bool singular = false;
+    int slots = 0;
+    size_t elem = 0;  // bytes of one complex value of the solve precision
+    pp::FftDesc fx{}, fy{};
+    int ty = 0, ldl = 0, ldy = 0, zb = 0;
+    size_t nper = 0;  // x-kernel workgroups per batch entry
+    // tables (uploaded into the workspace)
+    std::vector<unsigned char> blob;
+    size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
+    size_t table_rows = 0;
+    // workspace layout (byte offsets)
+    size_t o_scalars = 0, o_partial = 0, o_tables = 0, o_S = 0, o_r = 0, ws_bytes = 0;
+    const void* bound_ws = nullptr;
+    // last call
+    void* last_ws = nullptr;
+    hipStream_t last_stream = nullptr;
+    int last_iters = 0;
+    double last_rel = 0.0;
+    bool last_projected = false;
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;               // created lazily, reused
+    std::vector<std::pair<int, int>> marks;        // (event index, kernel group of the next launch)
+    double kms[4] = {0, 0, 0, 0};
+    int kcount[4] = {0, 0, 0, 0};
+    ~pp_plan_s() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int bc_code(char c) {
+    switch (c) {
+        case 'P': return pp::BC_P;
+        case 'N': return pp::BC_N;
+        case 'D': return pp::BC_D;
+        default: return -1;
+    }
+}
+
+bool factor23(int n) {
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+// Radix plan: as many radix-8 stages as possible (two radix-4 stages instead
+// of an 8 and a 2), then radix 3.
+pp::FftDesc radix_plan(int n) {
+    pp::FftDesc d{};
+    d.n = n;
+    int a = 0, b = 0, m = n;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    int s = 0;
+    int n8 = a / 3, rem = a % 3;
+    if (rem == 1 && n8 >= 1) {
+        for (int i = 0; i < n8 - 1; ++i) d.radix[s++] = 8;
+        d.radix[s++] = 4;
+        d.radix[s++] = 4;
+    } else {
+        for (int i = 0; i < n8; ++i) d.radix[s++] = 8;
+        if (rem == 1) d.radix[s++] = 2;
+        if (rem == 2) d.radix[s++] = 4;
+    }
+    for (int i = 0; i < b; ++i) d.radix[s++] = 3;
+    d.nstages = s;
+    return d;
+}
+
+const long double kPi = 3.141592653589793238462643383279502884L;
+
+// cos and sin of pi * num / den with num reduced modulo 2 den first.
+void cos_sin_pi(long long num, long long den, double* c, double* s) {
+    long long r = num % (2 * den);
+    if (r < 0) r += 2 * den;
+    const long double t = kPi * (long double)r / (long double)den;
+    *c = (double)cosl(t);
+    *s = (double)sinl(t);
+}
+
+// Table eig for one direction: mode k of n cells, spacing h.
+double eigenvalue(int kind, int k, int n, double h) {
+    long long num = 0;
+    if (kind == pp::BC_P) num = 2LL * k;
+    else if (kind == pp::BC_N) num = k;
+    else num = (long long)k + 1;
+    // -2 + 2 cos(pi num / n) = -4 sin^2(pi num / (2 n))
+    long long r = num % (2LL * n);
+    const long double half = kPi * (long double)r / (2.0L * (long double)n);
+    const long double s = sinl(half);
+    return (double)(-4.0L * s * s / ((long double)h * (long double)h));
+}
+
+template <typename T> struct Emit {
+    std::vector<unsigned char>& blob;
+    size_t put(size_t bytes) {
+        const size_t off = align_up(blob.size());
+        blob.resize(off + bytes, 0);
+        return off;
+    }
+    cplx<T>* cp(size_t off) { return reinterpret_cast<cplx<T>*>(blob.data() + off); }
+};
+
+// Reciprocal pivots of one z line.  body = w_0 .. w_{nz-2} until the value
+// stops changing; wl = w_{nz-1}; tail = first index from which the rounded
+// body value equals the rounded value at nz-2.
+template <typename T> struct Line {
+    std::vector<T> body;
+    T winf = 0, wlast = 0;
+    int tail = 0;
+};
+
+template <typename T>
+void pivots(double lam, int nz, double hz, int bz0, int bz1, bool pinned, Line<T>* out) {
+    const double bmid = -2.0 + hz * hz * lam;
+    const double d0 = (bz0 == pp::BC_D) ? -1.0 : 1.0;
+    const double d1 = (bz1 == pp::BC_D) ? -1.0 : 1.0;
+    out->body.clear();
+    if (nz == 1) {
+        out->wlast = pinned ? T(0) : (T)(1.0 / (bmid + d0 + d1));
+        out->winf = 0;
+        out->tail = 0;
+        return;
+    }
+    std::vector<double> seq;
+    seq.reserve(64);
+    double prev = pinned ? 0.0 : 1.0 / (bmid + d0);
+    seq.push_back(prev);
+    for (int z = 1; z <= nz - 2; ++z) {
+        const double w = 1.0 / (bmid - prev);
+        seq.push_back(w);
+        if (w == prev) break;  // fixed point: every later body value is the same
+        prev = w;
+    }
+    const double wend = seq.back();  // value at index nz-2
+    out->wlast = (T)(1.0 / ((bmid + d1) - wend));
+    out->winf = (T)wend;
+    int L = (int)seq.size();
+    while (L > 0 && (T)seq[L - 1] == out->winf) --L;
+    out->tail = L;
+    out->body.resize(L);
+    for (int i = 0; i < L; ++i) out->body[i] = (T)seq[i];
+}
+
+template <typename T> void build_tables(pp_plan p) {
+    p->blob.clear();
+    Emit<T> em{p->blob};
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    auto twiddles = [&](int n, size_t* tw, size_t* mkt) {
+        *tw = em.put(sizeof(cplx<T>) * n);
+        for (int j = 0; j < n; ++j) {
+            double c, s;
+            cos_sin_pi(2LL * j, n, &c, &s);  // exp(-2 pi i j / n)
+            em.cp(*tw)[j] = pp::mk<T>((T)c, (T)-s);
+        }
+        *mkt = em.put(sizeof(cplx<T>) * n);
+        for (int k = 0; k < n; ++k) {
+            double c, s;
+            cos_sin_pi(k, 2LL * n, &c, &s);  // exp(-i pi k / (2 n))
+            em.cp(*mkt)[k] = pp::mk<T>((T)c, (T)-s);
+        }
+    };
+    twiddles(nx, &p->t_twx, &p->t_mkx);
+    twiddles(ny, &p->t_twy, &p->t_mky);
+
+    std::vector<double> lamx(nx), lamy(ny);
+    for (int k = 0; k < nx; ++k) lamx[k] = eigenvalue(p->bx, k, nx, p->h[0]);
+    for (int k = 0; k < ny; ++k) lamy[k] = eigenvalue(p->by, k, ny, p->h[1]);
+
+    // kx of part `part` of slot m (-1: padding column of an odd nx)
+    auto kx_of = [&](int m, int part) -> int {
+        if (p->bx == pp::BC_P) {
+            if (m == 0) return part == 0 ? 0 : ((nx % 2 == 0) ? nx / 2 : -1);
+            return m;
+        }
+        const int k = 2 * m + part;
+        if (k >= nx) return -1;
+        return p->bx == pp::BC_D ? nx - 1 - k : k;  // DST columns are stored reversed
+    };
+
+    const int slots = p->slots;
+    std::vector<int> rowoff(slots), lmax(slots);
+    std::vector<T> winf((size_t)slots * ny * 2), wlast((size_t)slots * ny * 2);
+    std::vector<std::vector<Line<T>>> lines(slots);
+    size_t rows = 0;
+    for (int m = 0; m < slots; ++m) {
+        const bool pairslot = (p->bx != pp::BC_P) || (m == 0);
+        const bool sep = (p->by == pp::BC_P) && pairslot;
+        lines[m].resize((size_t)ny * 2);
+        int lm = 0;
+        for (int e = 0; e < ny; ++e) {
+            for (int part = 0; part < 2; ++part) {
+                int kx, ky;
+                if (sep && e != 0 && 2 * e != ny) {
+                    kx = kx_of(m, e < ny - e ? 0 : 1);
+                    ky = e;  // periodic eigenvalues are symmetric in ky <-> ny-ky
+                } else {
+                    kx = kx_of(m, part);
+                    ky = (p->by == pp::BC_D) ? ny - 1 - e : e;  // DST entries are stored reversed
+                }
+                Line<T>& ln = lines[m][(size_t)e * 2 + part];
+                if (kx < 0) {
+                    ln.body.clear();
+                    ln.winf = 0;
+                    ln.wlast = 0;
+                    ln.tail = 0;
+                } else {
+                    const bool pinned = p->singular && m == 0 && e == 0 && part == 0;
+                    pivots<T>(lamx[kx] + lamy[ky], nz, p->h[2], p->bz0, p->bz1, pinned, &ln);
+                }
+                winf[((size_t)m * ny + e) * 2 + part] = ln.winf;
+                wlast[((size_t)m * ny + e) * 2 + part] = ln.wlast;
+                lm = std::max(lm, ln.tail);
+            }
+        }
+        rowoff[m] = (int)rows;
+        lmax[m] = lm;
+        rows += lm;
+    }
+    p->table_rows = rows;
+    p->t_rowoff = em.put(sizeof(int) * slots);
+    std::memcpy(p->blob.data() + p->t_rowoff, rowoff.data(), sizeof(int) * slots);
+    p->t_lmax = em.put(sizeof(int) * slots);
+    std::memcpy(p->blob.data() + p->t_lmax, lmax.data(), sizeof(int) * slots);
+    p->t_winf = em.put(sizeof(T) * winf.size());
+    std::memcpy(p->blob.data() + p->t_winf, winf.data(), sizeof(T) * winf.size());
+    p->t_wlast = em.put(sizeof(T) * wlast.size());
+    std::memcpy(p->blob.data() + p->t_wlast, wlast.data(), sizeof(T) * wlast.size());
+    p->t_wrows = em.put(sizeof(T) * 2 * std::max<size_t>(rows, 1) * ny);
+    T* wr = reinterpret_cast<T*>(p->blob.data() + p->t_wrows);
+    for (int m = 0; m < slots; ++m) {
+        for (int z = 0; z < lmax[m]; ++z) {
+            T* row = wr + (size_t)(rowoff[m] + z) * ny * 2;
+            for (int e = 0; e < ny; ++e) {
+                for (int part = 0; part < 2; ++part) {
+                    const Line<T>& ln = lines[m][(size_t)e * 2 + part];
+                    row[e * 2 + part] = (z < ln.tail) ? ln.body[z] : ln.winf;
+                }
+            }
+        }
+    }
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+template <typename T> pp::XArgs<T> make_xargs(pp_plan p, unsigned char* ws) {
+    pp::XArgs<T> a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.slots = p->slots;
+    a.bx = p->bx;
+    a.ty = p->ty;
+    a.ldl = p->ldl;
+    a.fx = p->fx;
+    unsigned char* t = ws + p->o_tables;
+    a.twx = reinterpret_cast<const cplx<T>*>(t + p->t_twx);
+    a.mkx = reinterpret_cast<const cplx<T>*>(t + p->t_mkx);
+    return a;
+}
+
+// Per-batch arrays after the fixed scalars: [0, B) mean of the right-hand side
+// of the current solve, [B, 2B) mean of the zero-mode solution line, [2B, 3B)
+// gauge shift of the refinement loop, [3B, 4B) mean of the source f.
+template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool demean) {
+    pp::MidArgs<T> a{};
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.slots = p->slots;
+    a.bx = p->bx;
+    a.by = p->by;
+    a.ldy = p->ldy;
+    a.zb = p->zb;
+    a.singular = p->singular ? 1 : 0;
+    a.project = project ? 1 : 0;
+    a.demean = demean ? 1 : 0;
+    a.scale = (T)(p->h[2] * p->h[2] / ((double)p->nx * (double)p->ny));
+    a.hz2 = p->h[2] * p->h[2];
+    a.fy = p->fy;
+    unsigned char* t = ws + p->o_tables;
+    a.twy = reinterpret_cast<const cplx<T>*>(t + p->t_twy);
+    a.mky = reinterpret_cast<const cplx<T>*>(t + p->t_mky);
+    a.rowoff = reinterpret_cast<const int*>(t + p->t_rowoff);
+    a.lmax = reinterpret_cast<const int*>(t + p->t_lmax);
+    a.wrows = reinterpret_cast<const cplx<T>*>(t + p->t_wrows);
+    a.winf = reinterpret_cast<const cplx<T>*>(t + p->t_winf);
+    a.wlast = reinterpret_cast<const cplx<T>*>(t + p->t_wlast);
+    double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
+    a.mu = sc + pp::SC_COUNT + 3 * p->batch;
+    a.cmean = sc + pp::SC_COUNT + p->batch;
+    return a;
+}
+
+// Record a timing event before a launch of kernel group `group` (-1: end of a
+// sequence).  No-op unless timing is on.
+pp_status mark(pp_plan p, hipStream_t s, int group) {
+    if (!p->timing) return PP_OK;
+    const size_t idx = p->marks.size();
+    if (idx >= p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return PP_ERR_HIP;
+        p->ev_pool.push_back(e);
+    }
+    if (hipEventRecord(p->ev_pool[idx], s) != hipSuccess) return PP_ERR_HIP;
+    p->marks.emplace_back((int)idx, group);
+    return PP_OK;
+}
+
+// Fold the recorded marks into the per-group accumulators.
+pp_status collect(pp_plan p) {
+    if (p->marks.empty()) return PP_OK;
+    if (hipEventSynchronize(p->ev_pool[p->marks.back().first]) != hipSuccess) return PP_ERR_HIP;
+    for (size_t i = 0; i + 1 < p->marks.size(); ++i) {
+        const int g = p->marks[i].second;
+        if (g < 0) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev_pool[p->marks[i].first], p->ev_pool[p->marks[i + 1].first]) != hipSuccess)
+            return PP_ERR_HIP;
+        p->kms[g] += ms;
+        p->kcount[g] += 1;
+    }
+    p->marks.clear();
+    return PP_OK;
+}
+
+#define PP_HIP(call)                          \
+    do {                                      \
+        if ((call) != hipSuccess) return PP_ERR_HIP; \
+    } while (0)
+
+template <typename T, typename Tio>
+pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStream_t s, bool project, bool demean) {
+    pp::XArgs<T> xa = make_xargs<T>(p, ws);
+    pp::MidArgs<T> ma = make_midargs<T>(p, ws, project, demean);
+    double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
+    double* partial = reinterpret_cast<double*>(ws + p->o_partial);
+    cplx<T>* S = reinterpret_cast<cplx<T>*>(ws + p->o_S);
+    const double npts = (double)p->nx * p->ny * p->nz;
+    pp_status st;
+    if ((st = mark(p, s, 0)) != PP_OK) return st;
+    PP_HIP((pp::launch_xfwd<T, Tio>(f, S, partial, xa, p->batch, s)));
+    if ((st = mark(p, s, 3)) != PP_OK) return st;
+    PP_HIP(pp::launch_finalize_xfwd(partial, (int)p->nper, p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
+                                    sc + pp::SC_MAXF, s));
+    if ((st = mark(p, s, 1)) != PP_OK) return st;
+    PP_HIP(pp::launch_mid<T>(S, ma, p->batch, s));
+    if ((st = mark(p, s, 2)) != PP_OK) return st;
+    PP_HIP((pp::launch_xinv<T, Tio>(S, u, xa, p->batch, sc + pp::SC_COUNT + p->batch, s)));
+    return mark(p, s, -1);
+}
+
+pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, hipStream_t s, bool project,
+                      bool demean) {
+    pp::XArgs<float> xa = make_xargs<float>(p, ws);
+    pp::MidArgs<float> ma = make_midargs<float>(p, ws, project, demean);
+    double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
+    double* partial = reinterpret_cast<double*>(ws + p->o_partial);
+    cplx<float>* S = reinterpret_cast<cplx<float>*>(ws + p->o_S);
+    float* r = reinterpret_cast<float*>(ws + p->o_r);
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    const double npts = (double)n;
+    // gauge region whose mean is held fixed across corrections:
+    // 1 = volume (zero-mean gauge), 2 = plane z = 0 (pinned gauge)
+    int region = 0;
+    double nregion = 0.0;
+    if (p->singular) {
+        region = demean ? 1 : 2;
+        nregion = demean ? npts : (double)p->nx * p->ny;
+    }
+    pp::ResidualArgs ra{};
+    ra.nx = p->nx;
+    ra.ny = p->ny;
+    ra.nz = p->nz;
+    ra.batch = p->batch;
+    for (int i = 0; i < 6; ++i) ra.bc[i] = bc_code(p->bc[i]);
+    ra.proj = p->singular ? (project ? 1 : 2) : 0;
+    ra.ihx2 = 1.0 / (p->h[0] * p->h[0]);
+    ra.ihy2 = 1.0 / (p->h[1] * p->h[1]);
+    ra.ihz2 = 1.0 / (p->h[2] * p->h[2]);
+
+    pp_status st;
+    if ((st = mark(p, s, 3)) != PP_OK) return st;
+    PP_HIP(pp::launch_ir_init(sc, p->batch, s));
+    PP_HIP(hipMemsetAsync(u, 0, sizeof(double) * n * p->batch, s));
+    if ((st = mark(p, s, 0)) != PP_OK) return st;
+    PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, s)));
+    if ((st = mark(p, s, 3)) != PP_OK) return st;
+    PP_HIP(pp::launch_finalize_xfwd(partial, (int)p->nper, p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
+                                    sc + pp::SC_MAXF, s));
+    if ((st = mark(p, s, 1)) != PP_OK) return st;
+    PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
+    ma.mu = sc + pp::SC_COUNT;   // corrections project their own right-hand side
+    if ((st = mark(p, s, 2)) != PP_OK) return st;
+    PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, s));
+    if ((st = mark(p, s, 3)) != PP_OK) return st;
+    PP_HIP(pp::launch_finalize_update(partial, (int)p->nper, p->batch, nregion, sc, 1, s));
+    if ((st = mark(p, s, -1)) != PP_OK) return st;
+    p->last_iters = 0;
+    p->last_rel = 1.0;
+    for (int it = 1; it <= p->ir_max; ++it) {
+        if ((st = mark(p, s, 3)) != PP_OK) return st;
+        PP_HIP(pp::launch_residual(f, u, r, ra, sc, s));
+        if ((st = mark(p, s, 0)) != PP_OK) return st;
+        PP_HIP((pp::launch_xfwd<float, float>(r, S, partial, xa, p->batch, s)));
+        if ((st = mark(p, s, 3)) != PP_OK) return st;
+        PP_HIP(pp::launch_finalize_xfwd(partial, (int)p->nper, p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
+        if ((st = mark(p, s, 1)) != PP_OK) return st;
+        PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
+        if ((st = mark(p, s, 2)) != PP_OK) return st;
+        PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, s));
+        if ((st = mark(p, s, 3)) != PP_OK) return st;
+        PP_HIP(pp::launch_finalize_update(partial, (int)p->nper, p->batch, nregion, sc, 0, s));
+        if ((st = mark(p, s, -1)) != PP_OK) return st;
+        double h[8];
+        PP_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+        PP_HIP(hipStreamSynchronize(s));
+        p->last_iters = it;
+        const double maxf = h[pp::SC_MAXF], rel = h[pp::SC_REL], relprev = h[pp::SC_RELPREV];
+        p->last_rel = rel;
+        if ((st = collect(p)) != PP_OK) return st;
+        if (!std::isfinite(maxf) || !std::isfinite(rel)) return PP_ERR_NONFINITE;
+        // estimated error after this correction: the next correction, predicted
+        // from the contraction of the last two
+        const double rho = relprev > 0.0 ? std::min(1.0, rel / relprev) : 1.0;
+        if (rel == 0.0 || rel * rho <= p->ir_tol) return PP_OK;
+    }
+    return PP_ERR_NOT_CONVERGED;
+}
+
+pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* stream, bool adjoint) {
+    if (!p || !f || !u) return PP_ERR_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return PP_ERR_WORKSPACE;
+    const size_t n = (size_t)p->nx * p->ny * p->nz * p->batch;
+    const size_t io = (p->dtype == PP_F32) ? sizeof(float) : sizeof(double);
+    if (((uintptr_t)f % io) != 0 || ((uintptr_t)u % io) != 0) return PP_ERR_ARG;
+    if (overlap(f, n * io, u, n * io) || overlap(u, n * io, workspace, p->ws_bytes) ||
+        overlap(f, n * io, workspace, p->ws_bytes))
+        return PP_ERR_ALIAS;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+    if (p->bound_ws != workspace) {
+        PP_HIP(hipMemcpyAsync(ws + p->o_tables, p->blob.data(), p->blob.size(), hipMemcpyHostToDevice, s));
+        p->bound_ws = workspace;
+    }
+    // zero-mode treatment; the adjoint trades projection and mean shift
+    bool project, demean;
+    if (!adjoint) {
+        project = p->gauge != PP_GAUGE_PIN_RAW;
+        demean = p->gauge == PP_GAUGE_MEAN;
+    } else {
+        project = p->gauge == PP_GAUGE_MEAN;
+        demean = p->gauge != PP_GAUGE_PIN_RAW;
+    }
+    if (p->marks.size() > 4096) {
+        const pp_status st = collect(p);
+        if (st != PP_OK) return st;
+    }
+    p->last_ws = workspace;
+    p->last_stream = s;
+    p->last_iters = 0;
+    p->last_rel = 0.0;
+    p->last_projected = p->singular && project;
+    switch (p->dtype) {
+        case PP_F64:
+            return run_plain<double, double>(p, (const double*)f, (double*)u, ws, s, project, demean);
+        case PP_F32:
+            return run_plain<float, float>(p, (const float*)f, (float*)u, ws, s, project, demean);
+        case PP_F32_REFINED:
+            return run_refined(p, (const double*)f, (double*)u, ws, s, project, demean);
+    }
+    return PP_ERR_ARG;
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double h[3], pp_dtype dtype, int batch,
+                         pp_plan* out) {
+    if (!out) return PP_ERR_ARG;
+    *out = nullptr;
+    if (!bc || !h) return PP_ERR_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 || batch < 1) return PP_ERR_ARG;
+    if (dtype != PP_F64 && dtype != PP_F32 && dtype != PP_F32_REFINED) return PP_ERR_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!(h[d] > 0.0) || !std::isfinite(h[d])) return PP_ERR_ARG;
+    int code[6];
+    for (int i = 0; i < 6; ++i) {
+        code[i] = bc_code(bc[i]);
+        if (code[i] < 0) return PP_ERR_BC;
+    }
+    if (code[0] != code[1] || code[2] != code[3]) return PP_ERR_BC;
+    if (code[4] == pp::BC_P || code[5] == pp::BC_P) return PP_ERR_BC;
+    if (!factor23(nx) || !factor23(ny)) return PP_ERR_SIZE;
+    if (nx > 2048 || ny > pp::kThreads * pp::kMaxOwned) return PP_ERR_SIZE;
+    if ((long long)nz * batch > 65535) return PP_ERR_SIZE;
+
+    pp_plan p = new (std::nothrow) pp_plan_s;
+    if (!p) return PP_ERR_ARG;
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->batch = batch;
+    std::memcpy(p->bc, bc, 6);
+    std::memcpy(p->h, h, sizeof(double) * 3);
+    p->dtype = dtype;
+    p->bx = code[0];
+    p->by = code[2];
+    p->bz0 = code[4];
+    p->bz1 = code[5];
+    p->singular = (p->bx != pp::BC_D) && (p->by != pp::BC_D) && p->bz0 == pp::BC_N && p->bz1 == pp::BC_N;
+    p->slots = (nx + 1) / 2;
+    const bool f64 = (dtype == PP_F64);
+    p->elem = f64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+    p->fx = radix_plan(nx);
+    p->fy = radix_plan(ny);
+    p->ldl = pp::padded_len(nx);
+    p->ldy = pp::padded_len(ny);
+    const int cap = pp::kLdsBytes / (int)p->elem;
+    int lines = std::min(cap / p->ldl, (ny + 1) / 2);
+    p->zb = std::min(cap / p->ldy, nz);
+    if (lines < 1 || p->zb < 1) {
+        delete p;
+        return PP_ERR_SIZE;
+    }
+    p->ty = 2 * lines;
+    p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz;
+    if (f64) build_tables<double>(p);
+    else build_tables<float>(p);
+
+    const size_t n = (size_t)nx * ny * nz;
+    size_t off = 0;
+    p->o_scalars = off;
+    off = align_up(off + sizeof(double) * (pp::SC_COUNT + 4 * (size_t)batch));
+    p->o_partial = off;
+    off = align_up(off + sizeof(double) * 3 * p->nper * batch);
+    p->o_tables = off;
+    off = align_up(off + p->blob.size());
+    p->o_S = off;
+    off = align_up(off + p->elem * (size_t)batch * p->slots * nz * ny);
+    p->o_r = off;
+    if (dtype == PP_F32_REFINED) off = align_up(off + sizeof(float) * n * batch);
+    p->ws_bytes = off;
+    *out = p;
+    return PP_OK;
+}
+
+pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge) {
+    if (!p) return PP_ERR_ARG;
+    if (gauge != PP_GAUGE_MEAN && gauge != PP_GAUGE_PIN && gauge != PP_GAUGE_PIN_RAW) return PP_ERR_ARG;
+    p->gauge = gauge;
+    return PP_OK;
+}
+
+pp_status pp_plan_set_refinement(pp_plan p, double tol, int max_iter) {
+    if (!p || !(tol >= 0.0) || max_iter < 0) return PP_ERR_ARG;
+    p->ir_tol = tol;
+    p->ir_max = max_iter;
+    return PP_OK;
+}
+
+size_t pp_plan_workspace_bytes(pp_plan p) { return p ? p->ws_bytes : 0; }
+
+pp_status pp_solve(pp_plan p, const void* f, void* u, void* workspace, void* stream) {
+    return dispatch(p, f, u, workspace, stream, false);
+}
+
+pp_status pp_solve_adjoint(pp_plan p, const void* g, void* out, void* workspace, void* stream) {
+    return dispatch(p, g, out, workspace, stream, true);
+}
+
+pp_status pp_plan_last_info(pp_plan p, int* ir_iters, double* removed_mean, double* final_rel_update) {
+    if (!p) return PP_ERR_ARG;
+    if (ir_iters) *ir_iters = p->last_iters;
+    if (final_rel_update) *final_rel_update = p->last_rel;
+    if (!p->last_ws) {
+        if (removed_mean)
+            for (int b = 0; b < p->batch; ++b) removed_mean[b] = 0.0;
+        return PP_OK;
+    }
+    std::vector<double> sc(pp::SC_COUNT + 4 * (size_t)p->batch);
+    if (hipStreamSynchronize(p->last_stream) != hipSuccess) return PP_ERR_HIP;
+    if (hipMemcpy(sc.data(), (unsigned char*)p->last_ws + p->o_scalars, sizeof(double) * sc.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return PP_ERR_HIP;
+    bool finite = std::isfinite(sc[pp::SC_MAXF]);
+    for (int b = 0; b < p->batch; ++b) {
+        const double mu = sc[pp::SC_COUNT + 3 * p->batch + b];
+        finite = finite && std::isfinite(mu);
+        if (removed_mean) removed_mean[b] = p->last_projected ? mu : 0.0;
+    }
+    return finite ? PP_OK : PP_ERR_NONFINITE;
+}
+
+pp_status pp_plan_set_timing(pp_plan p, int on) {
+    if (!p) return PP_ERR_ARG;
+    p->timing = on != 0;
+    return PP_OK;
+}
+
+pp_status pp_plan_kernel_times(pp_plan p, double* ms, int* launches, int reset) {
+    if (!p) return PP_ERR_ARG;
+    const pp_status st = collect(p);
+    if (st != PP_OK) return st;
+    for (int g = 0; g < 4; ++g) {
+        if (ms) ms[g] = p->kms[g];
+        if (launches) launches[g] = p->kcount[g];
+        if (reset) {
+            p->kms[g] = 0.0;
+            p->kcount[g] = 0;
+        }
+    }
+    return PP_OK;
+}
+
+void pp_plan_destroy(pp_plan p) {
+    if (p) (void)collect(p);
+    delete p;
+}
+
+const char* pp_status_string(pp_status st) {
+    switch (st) {
+        case PP_OK: return "ok";
+        case PP_ERR_ARG: return "invalid argument";
+        case PP_ERR_BC: return "unsupported boundary conditions";
+        case PP_ERR_SIZE: return "unsupported grid size";
+        case PP_ERR_ALIAS: return "arrays overlap";
+        case PP_ERR_WORKSPACE: return "workspace null or misaligned";
+        case PP_ERR_HIP: return "HIP runtime error";
+        case PP_ERR_NOT_CONVERGED: return "refinement did not converge";
+        case PP_ERR_NONFINITE: return "non-finite value in the source";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

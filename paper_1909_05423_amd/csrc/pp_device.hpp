@@ -1,0 +1,245 @@
+// Device building blocks: complex arithmetic, radix-2/3/4/8 butterflies and a
+// batched mixed-radix Stockham FFT over lines held in LDS.
+//
+// The complex DFT is the primitive every real transform of the method is built
+// on (section "Boundary Conditions": pre-process, complex FFT, post-process).
+// Lines of length N = 2^a 3^b sit in LDS, one line every `ldl` elements, with
+// one spare slot after every 8 elements (pad()) to spread the power-of-two
+// strides of the first stages over the LDS banks.
+//
+// Stockham step (self-sorting, decimation in time), for a stage of radix R
+// after sub-transforms of length Ls have been formed, butterfly j in [0, N/R):
+//     k = j mod Ls,   inputs  x[j + t N/R] * w^(t k N/(Ls R)),  t = 0..R-1
+//     outputs y[(j - k) R + k + t Ls] = DFT_R(inputs)[t]
+// with w = exp(-2 pi i / N) (conjugated for the inverse).  After the last
+// stage the line holds the transform in natural order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pp {
+
+template <typename T> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+template <typename T> using cplx = typename vec2<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ cplx<T> mk(T re, T im) {
+    cplx<T> r;
+    r.x = re;
+    r.y = im;
+    return r;
+}
+// Complex helpers, generic over the two-component vector types (double2, float2).
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) {
+    V r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename V> __device__ __forceinline__ V csub(V a, V b) {
+    V r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+    V r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.y * b.x - a.x * b.y;
+    return r;
+}
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) {
+    V r;
+    r.x = a.x * s;
+    r.y = a.y * s;
+    return r;
+}
+
+// Multiply by -i (forward transforms) or +i (inverse transforms).
+template <bool INV, typename V> __device__ __forceinline__ V rot(V a) {
+    V r;
+    if (INV) {
+        r.x = -a.y;
+        r.y = a.x;
+    } else {
+        r.x = a.y;
+        r.y = -a.x;
+    }
+    return r;
+}
+
+__host__ __device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int padded_len(int n) { return n + ((n - 1) >> 3); }
+
+// Position of x[n] after the reordering that turns a DCT-II into one complex
+// DFT (even-indexed samples ascending, then odd-indexed samples descending;
+// Neumann subsection).  The inverse DCT-III reads its result back through the
+// same map.
+__device__ __forceinline__ int makhoul_pos(int n, int N) { return (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1); }
+
+// ---------------------------------------------------------------- butterflies
+template <bool INV, typename T> __device__ __forceinline__ void bfly2(cplx<T>* v) {
+    cplx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <bool INV, typename T> __device__ __forceinline__ void bfly4(cplx<T>* v) {
+    cplx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cplx<T> s13 = cadd(v[1], v[3]), d13 = rot<INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <bool INV, typename T> __device__ __forceinline__ void bfly8(cplx<T>* v) {
+    cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    bfly4<INV, T>(e);
+    bfly4<INV, T>(o);
+    const T r = T(0.70710678118654752440);  // 1/sqrt(2)
+    // o1 * w^1, o2 * w^2, o3 * w^3 with w = exp(-+ i pi / 4)
+    cplx<T> o1 = INV ? mk<T>((o[1].x - o[1].y) * r, (o[1].x + o[1].y) * r)
+                     : mk<T>((o[1].x + o[1].y) * r, (o[1].y - o[1].x) * r);
+    cplx<T> o2 = rot<INV>(o[2]);
+    cplx<T> o3 = INV ? mk<T>((-o[3].x - o[3].y) * r, (o[3].x - o[3].y) * r)
+                     : mk<T>((o[3].y - o[3].x) * r, (-o[3].x - o[3].y) * r);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <bool INV, typename T> __device__ __forceinline__ void bfly3(cplx<T>* v) {
+    const T h = T(0.86602540378443864676);  // sqrt(3)/2
+    cplx<T> t1 = cadd(v[1], v[2]);
+    cplx<T> t2 = mk<T>(v[0].x - T(0.5) * t1.x, v[0].y - T(0.5) * t1.y);
+    cplx<T> dd = csub(v[1], v[2]);
+    cplx<T> t3 = rot<INV>(mk<T>(h * dd.x, h * dd.y));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+}
+
+template <int R, bool INV, typename T> __device__ __forceinline__ void bfly(cplx<T>* v) {
+    if constexpr (R == 2) bfly2<INV, T>(v);
+    else if constexpr (R == 3) bfly3<INV, T>(v);
+    else if constexpr (R == 4) bfly4<INV, T>(v);
+    else bfly8<INV, T>(v);
+}
+
+// Radix plan of one transform length, fixed on the host.
+struct FftDesc {
+    int n;
+    int nstages;
+    int radix[16];
+};
+
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// One Stockham stage over `nlines` lines.  Every butterfly of the stage is
+// held in registers between the two barriers, so the update is in place.
+// MAXB bounds the butterflies one thread owns: nlines*N/R <= MAXB*NTH.
+template <int R, int MAXB, int NTH, bool INV, typename T>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int ldl, int nlines, int N, int Ls,
+                                          const cplx<T>* __restrict__ tw) {
+    const int nbf = N / R;
+    const int total = nlines * nbf;
+    const int step = N / (Ls * R);
+    const int tid = threadIdx.x;
+    cplx<T> v[MAXB][R];
+    int dline[MAXB], didx[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int bidx = tid + i * NTH;
+        dline[i] = -1;
+        if (bidx < total) {
+            const int line = bidx / nbf;
+            const int j = bidx - line * nbf;
+            const int k = j % Ls;
+            const cplx<T>* src = buf + line * ldl;
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[i][t] = src[pad(j + t * nbf)];
+            if (Ls > 1) {
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    const cplx<T> w = tw[t * k * step];
+                    v[i][t] = INV ? cmulc(v[i][t], w) : cmul(v[i][t], w);
+                }
+            }
+            bfly<R, INV, T>(v[i]);
+            dline[i] = line * ldl;
+            didx[i] = (j - k) * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        if (dline[i] >= 0) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[dline[i] + pad(didx[i] + t * Ls)] = v[i][t];
+        }
+    }
+    __syncthreads();
+}
+
+// Transform `nlines` lines of d.n complex values in LDS, in place.  EMAX is the
+// LDS capacity in complex elements (nlines * d.n <= EMAX).  Callers synchronise
+// before the call; the call ends with a barrier.
+template <int NTH, int EMAX, bool INV, typename T>
+__device__ void fft_lines(cplx<T>* buf, int ldl, int nlines, const FftDesc& d, const cplx<T>* __restrict__ tw) {
+    int Ls = 1;
+    for (int s = 0; s < d.nstages; ++s) {
+        const int R = d.radix[s];
+        if (R == 8) fft_stage<8, cdiv(EMAX, 8 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        else if (R == 4) fft_stage<4, cdiv(EMAX, 4 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        else if (R == 3) fft_stage<3, cdiv(EMAX, 3 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        else fft_stage<2, cdiv(EMAX, 2 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        Ls *= R;
+    }
+}
+
+// Sum of a double over the block (wave64 shuffles, then LDS across waves).
+// Result valid in thread 0.
+template <int NTH> __device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < NTH / 64; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+template <int NTH> __device__ __forceinline__ double block_max(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < NTH / 64; ++w) s = fmax(s, red[w]);
+    }
+    __syncthreads();
+    return s;
+}
+
+}  // namespace pp

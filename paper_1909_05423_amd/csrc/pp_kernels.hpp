@@ -1,0 +1,114 @@
+// Kernel argument blocks and host launchers shared by the plan code and the
+// kernel sources.  Internal to the library: the public ABI is include/ppsolve.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+#include "pp_device.hpp"
+
+namespace pp {
+
+enum Bc : int { BC_P = 0, BC_N = 1, BC_D = 2 };
+
+// LDS budget of one workgroup (bytes) and the threads of every transform kernel.
+constexpr int kLdsBytes = 73728;
+constexpr int kThreads = 256;
+// Entries (spectral y positions) one thread of the z-march owns: ny <= kThreads * kMaxOwned.
+constexpr int kMaxOwned = 8;
+
+template <typename T> constexpr int lds_elems() { return kLdsBytes / (int)sizeof(cplx<T>); }
+
+// x-direction kernels: a workgroup owns `ty` consecutive rows (y0 .. y0+ty-1)
+// of one z plane of one batch entry, packed two rows per complex line.
+template <typename T> struct XArgs {
+    int nx, ny, nz, slots;   // slots = ceil(nx/2) spectral columns per row
+    int bx;                  // boundary type along x (Bc)
+    int ty;                  // rows per workgroup (even)
+    int ldl;                 // LDS line stride (padded_len(nx))
+    FftDesc fx;              // radix plan for nx
+    const cplx<T>* twx;      // exp(-2 pi i j / nx), j < nx
+    const cplx<T>* mkx;      // exp(-i pi k / (2 nx)), k < nx
+};
+
+// Solution mode of the inverse x kernel.
+enum XinvMode : int { XINV_STORE = 0, XINV_UPDATE = 1 };
+
+// z-march kernel: one workgroup per (spectral x column, batch entry).
+template <typename T> struct MidArgs {
+    int ny, nz, slots;
+    int bx, by;
+    int ldy;                 // LDS line stride (padded_len(ny))
+    int zb;                  // z planes per LDS chunk
+    int singular;            // zero mode present (slot 0, entry 0, real part)
+    int project;             // subtract the source mean from the zero-mode line
+    int demean;              // report the mean of the zero-mode solution (subtracted by the x inverse)
+    T scale;                 // hz^2 / (nx ny): all transform normalisations and the z-system scaling
+    double hz2;              // hz^2 (projection constant = hz^2 * mean(f))
+    FftDesc fy;
+    const cplx<T>* twy;      // exp(-2 pi i j / ny)
+    const cplx<T>* mky;      // exp(-i pi k / (2 ny))
+    const int* rowoff;       // per slot: first table row
+    const int* lmax;         // per slot: rows stored (z < lmax reads the table)
+    const cplx<T>* wrows;    // [row][ny] (w_re, w_im) reciprocal pivots
+    const cplx<T>* winf;     // [slot][ny] converged reciprocal pivot
+    const cplx<T>* wlast;    // [slot][ny] reciprocal pivot of the last row
+    const double* mu;        // [batch] source means
+    double* cmean;           // [batch] mean of the zero-mode solution line (output)
+};
+
+// IR residual r = scale * (f - c - L_h u) in float, where c is the part of f
+// outside the range of L_h in a singular problem (known from the source mean):
+//   proj 0: none (non-singular); 1: mean(f) everywhere (projected gauges);
+//   2: nz * mean(f) on the plane z = 0 only (pinned gauge without projection).
+struct ResidualArgs {
+    int nx, ny, nz, batch;
+    int bc[6];
+    int proj;
+    double ihx2, ihy2, ihz2;
+};
+
+// --- launchers (return hipError_t of the launch) -----------------------------
+template <typename T, typename Tin>
+hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch, hipStream_t s);
+
+template <typename T, typename Tout>
+hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
+                       hipStream_t s);
+
+// Refinement update: u += d / scale - gauge_shift[b]; partials (sum over the
+// gauge region of the new u, max |d / scale|, max |u_new|) per workgroup.
+hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float>& a, int batch,
+                              const double* scalars, int gauge_region, double* partial, hipStream_t s);
+
+template <typename T>
+hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);
+
+// Finalise the x-forward partials: mu[b] = sum / npts, scalars[SC_MAXF] = max |f|.
+hipError_t launch_finalize_xfwd(const double* partial, int nper, int batch, double npts, double* mu,
+                                double* maxf, hipStream_t s);
+
+// Finalise the refinement-update partials into the scalar block and choose the
+// next residual scale.
+hipError_t launch_finalize_update(const double* partial, int nper, int batch, double nregion, double* scalars,
+                                  int first, hipStream_t s);
+
+hipError_t launch_residual(const double* f, const double* u, float* r, const ResidualArgs& a,
+                           const double* scalars, hipStream_t s);
+
+// Initial scalars of the refinement loop (unit scale, no gauge shift).
+hipError_t launch_ir_init(double* scalars, int batch, hipStream_t s);
+
+// Scalar block layout (doubles) used by the refinement loop.
+enum Scalar : int {
+    SC_MAXF = 0,      // max |f|
+    SC_MAXD = 1,      // max |correction| of the last update
+    SC_MAXU = 2,      // max |u| after the last update
+    SC_REL = 3,       // SC_MAXD / SC_MAXU
+    SC_RELPREV = 4,   // previous SC_REL
+    SC_SCALE = 5,     // residual scale of the current step (power of two)
+    SC_INVSCALE = 6,  // 1 / SC_SCALE
+    SC_COUNT = 16     // per-batch arrays follow
+};
+
+}  // namespace pp

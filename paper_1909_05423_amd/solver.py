@@ -1,0 +1,120 @@
+"""Python face of the solver: a Plan owning its device workspace, solve/adjoint
+calls on torch tensors, and a torch.autograd.Function whose backward is the
+hand-written adjoint solve.
+
+Tensors are device-resident, C-contiguous, shaped (batch, nz, ny, nx) (or
+(nz, ny, nx) for batch 1), float64 for 'f64' and 'f32_refined', float32 for
+'f32'.  Every launch goes on torch's current HIP stream.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+DTYPES = {"f64": (_lib.PP_F64, torch.float64), "f32": (_lib.PP_F32, torch.float32),
+          "f32_refined": (_lib.PP_F32_REFINED, torch.float64)}
+GAUGES = {"mean": _lib.PP_GAUGE_MEAN, "pin": _lib.PP_GAUGE_PIN, "pin_raw": _lib.PP_GAUGE_PIN_RAW}
+
+
+class Plan:
+    """A solve plan for grids of shape (nz, ny, nx) with boundary string bc
+    (x-, x+, y-, y+, z-, z+ from 'P', 'D', 'N') and spacings h = (hx, hy, hz)."""
+
+    def __init__(self, shape, bc, h, dtype="f64", batch=1, gauge="mean", device=None,
+                 refine_tol=None, refine_max_iter=None):
+        lib = _lib.load()
+        nz, ny, nx = (int(v) for v in shape)
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        if gauge not in GAUGES:
+            raise ValueError(f"gauge must be one of {sorted(GAUGES)}")
+        if not isinstance(bc, str) or len(bc) != 6:
+            raise ValueError("bc must be a 6-character string")
+        self.shape = (nz, ny, nx)
+        self.bc = bc
+        self.h = tuple(float(v) for v in h)
+        self.dtype = dtype
+        self.batch = int(batch)
+        self.gauge = gauge
+        self.code, self.torch_dtype = DTYPES[dtype]
+        hh = (ctypes.c_double * 3)(*self.h)
+        handle = ctypes.c_void_p()
+        _lib.check(lib.pp_plan_create(nx, ny, nz, bc.encode(), hh, self.code, self.batch, ctypes.byref(handle)),
+                   "pp_plan_create")
+        self._handle = handle
+        _lib.check(lib.pp_plan_set_gauge(handle, GAUGES[gauge]), "pp_plan_set_gauge")
+        if refine_tol is not None or refine_max_iter is not None:
+            _lib.check(lib.pp_plan_set_refinement(handle, 1e-13 if refine_tol is None else float(refine_tol),
+                                                  8 if refine_max_iter is None else int(refine_max_iter)),
+                       "pp_plan_set_refinement")
+        self.workspace_bytes = int(lib.pp_plan_workspace_bytes(handle))
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.device = device
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().pp_plan_destroy(h)
+            except Exception:
+                pass
+            self._handle = None
+
+    def _check_tensor(self, t, name):
+        full = (self.batch,) + self.shape
+        if tuple(t.shape) != full and not (self.batch == 1 and tuple(t.shape) == self.shape):
+            raise ValueError(f"{name} must have shape {full}, got {tuple(t.shape)}")
+        if t.dtype != self.torch_dtype:
+            raise TypeError(f"{name} must be {self.torch_dtype}, got {t.dtype}")
+        if t.device != self.workspace.device:
+            raise ValueError(f"{name} must live on {self.workspace.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def _run(self, fn, src, out, what):
+        self._check_tensor(src, "input")
+        if out is None:
+            out = torch.empty_like(src)
+        self._check_tensor(out, "out")
+        stream = torch.cuda.current_stream(self.workspace.device).cuda_stream
+        status = fn(self._handle, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                    ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_void_p(stream))
+        _lib.check(status, what)
+        return out
+
+    def solve(self, f, out=None):
+        """u with L_h u = f (see include/ppsolve.h for the zero-mode gauge)."""
+        return self._run(_lib.load().pp_solve, f, out, "pp_solve")
+
+    def adjoint(self, g, out=None):
+        """G^T g for the map G: f -> u of solve()."""
+        return self._run(_lib.load().pp_solve_adjoint, g, out, "pp_solve_adjoint")
+
+    def last_info(self):
+        """(refinement steps, removed source mean per batch entry, last relative correction)."""
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        means = (ctypes.c_double * self.batch)()
+        _lib.check(_lib.load().pp_plan_last_info(self._handle, ctypes.byref(it), means, ctypes.byref(rel)),
+                   "pp_plan_last_info")
+        return it.value, list(means), rel.value
+
+
+class PoissonSolve(torch.autograd.Function):
+    """u = G f with dJ/df = G^T dJ/du computed by the adjoint solve."""
+
+    @staticmethod
+    def forward(ctx, f, plan):
+        ctx.plan = plan
+        return plan.solve(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        return ctx.plan.adjoint(grad_u.contiguous()), None
+
+
+def poisson_solve(f, plan):
+    return PoissonSolve.apply(f, plan)

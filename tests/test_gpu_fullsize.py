@@ -1,0 +1,228 @@
+"""GPU checks at the full workload sizes, in the launch configuration bench.py
+times (one plan per workload, default tiling).
+
+Where the oracle cannot run at full size, results are compared with exact
+discrete solutions (sources built from discrete eigenmodes, evaluated by
+oracle.closed_form at sampled points) or checked through properties that hold
+at any size (backward error, agreement of the refined and double solves).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import closed_form
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan_solve(wl, dtype="f64", f=None, adjoint=False, gauge="mean"):
+    import torch
+    from paper_1909_05423_amd import Plan
+    f = wl["f"] if f is None else f
+    plan = Plan(wl["shape"], wl["bc"], wl["h"], dtype=dtype, batch=f.shape[0], gauge=gauge)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    fd = torch.from_numpy(np.ascontiguousarray(f)).to("cuda", tdt)
+    u = plan.adjoint(fd) if adjoint else plan.solve(fd)
+    torch.cuda.synchronize()
+    return u, plan
+
+
+def _sample_points(shape, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, n, count) for n in shape], axis=1)
+    corners = [(0, 0, 0), tuple(n - 1 for n in shape), (0, shape[1] - 1, 0), (shape[0] - 1, 0, shape[2] - 1)]
+    return np.concatenate([pts, np.array(corners)], axis=0)
+
+
+def _at(u, b, pts):
+    import torch
+    idx = torch.as_tensor(pts, device=u.device)
+    return u[b][idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+
+
+def test_mms_ppd_32_full_oracle_and_closed_form():
+    from gpu_util import banner, rel_max
+    banner("mms_ppd 32^3")
+    wl = workloads.make("mms_ppd")
+    u, _ = _plan_solve(wl)
+    u = u.cpu().numpy()
+    assert rel_max(u, oracle.solve(wl["f"], wl["bc"], wl["h"])) < 1e-12
+    ratio = closed_form.manufactured_ratio(wl["source_modes"][0]["w"], wl["h"])
+    assert rel_max(u[0], ratio * wl["ustar"]) < 1e-12
+
+
+def test_noisy_dnn_256_full_oracle():
+    from gpu_util import banner, rel_max
+    banner("noisy_dnn 256^3 f64 + f32")
+    wl = workloads.make("noisy_dnn")
+    uo = oracle.solve(wl["f"], wl["bc"], wl["h"])
+    u, _ = _plan_solve(wl)
+    assert rel_max(u.cpu().numpy(), uo) < 1e-12
+    f32 = wl["f"].astype(np.float32)
+    u32, _ = _plan_solve(wl, dtype="f32", f=f32)
+    assert rel_max(u32.double().cpu().numpy(), uo) < 1e-5
+
+
+def _ppn_mode_source(shape, seed, count=64):
+    """Sum of periodic-x,y / Neumann-z eigenmodes (no constant mode): exact solution known."""
+    rng = np.random.default_rng(seed)
+    modes, amps = [], []
+    while len(modes) < count:
+        kx, ky = rng.integers(-8, 9, 2)
+        kz = rng.integers(0, 9)
+        if kx == 0 and ky == 0 and kz == 0:
+            continue
+        modes.append(dict(form="xywave", w=(2 * np.pi * kx, 2 * np.pi * ky, np.pi * kz),
+                          phase=(rng.uniform(0, 2 * np.pi), 0.0)))
+        amps.append(rng.standard_normal())
+    return modes, np.array(amps)
+
+
+def test_div_ppn_512_backward_error_and_refined():
+    import torch
+    from gpu_util import banner
+    banner("div_ppn 512^3 f64 backward error, refined agreement")
+    wl = workloads.make("div_ppn")
+    u, plan = _plan_solve(wl)
+    un = u.cpu().numpy()
+    fp = wl["f"] - wl["f"].mean()
+    eta = oracle.backward_error(fp[0], un[0], wl["bc"], wl["h"])
+    assert eta < 1e-14, eta
+    assert abs(un.mean()) < 1e-14 * np.abs(un).max()
+    ur, plan_r = _plan_solve(wl, dtype="f32_refined")
+    its, means, rel = plan_r.last_info()
+    d = float((ur - u).abs().max() / u.abs().max())
+    banner(f"refined corrections {its}, diff vs f64 {d:.2e}")
+    assert d < 1e-12
+    u32, _ = _plan_solve(wl, dtype="f32", f=wl["f"].astype(np.float32))
+    assert float((u32.double() - u).abs().max() / u.abs().max()) < 1e-5
+    del u, ur, u32
+    torch.cuda.empty_cache()
+
+
+def test_div_ppn_recipe_128_elementwise():
+    from gpu_util import banner, rel_max
+    banner("div_ppn recipe at 128^3 vs oracle")
+    wl = workloads.make("div_ppn", shape=(128, 128, 128))
+    uo = oracle.solve(wl["f"], wl["bc"], wl["h"])
+    for gauge in ("mean", "pin", "pin_raw"):
+        u, _ = _plan_solve(wl, gauge=gauge)
+        assert rel_max(u.cpu().numpy(), oracle.solve(wl["f"], wl["bc"], wl["h"], gauge)) < 1e-12
+    u, _ = _plan_solve(wl, dtype="f32_refined")
+    assert rel_max(u.cpu().numpy(), uo) < 1e-12
+
+
+def test_ppn_512_closed_form_sampled():
+    """Full-size 512^3 periodic/Neumann parity against the exact discrete solution."""
+    from gpu_util import banner, rel_max
+    banner("ppn 512^3 closed-form modes")
+    shape = (512, 512, 512)
+    modes, amps = _ppn_mode_source(shape, 31)
+    src = workloads._eval_modes(modes, amps, shape)[None]
+    wl = dict(shape=shape, bc="PPPPNN", h=(1 / 512,) * 3, f=src)
+    pts = _sample_points(shape, 4096, 32)
+    exact = closed_form.solve_mode_sum_at(modes, amps, shape, (1.0, 1.0, 1.0), pts)
+    for dtype, tol in (("f64", 1e-12), ("f32_refined", 1e-12)):
+        u, _ = _plan_solve(wl, dtype=dtype)
+        assert rel_max(_at(u, 0, pts), exact) < tol, dtype
+    u, _ = _plan_solve(wl, dtype="f32", f=src.astype(np.float32))
+    assert rel_max(_at(u, 0, pts), exact) < 1e-5
+
+
+def test_modes_ppd_1024x1024x512_refined():
+    import torch
+    from gpu_util import banner, rel_max
+    banner("modes_ppd 1024x1024x512: f64, f32, f32+refine vs closed form")
+    wl = workloads.make("modes_ppd")
+    modes, amps = wl["modes"][0]
+    pts = _sample_points(wl["shape"], 4096, 41)
+    exact = closed_form.solve_mode_sum_at(modes, amps, wl["shape"], wl["lengths"], pts)
+    u, _ = _plan_solve(wl, dtype="f32_refined")
+    err_r = rel_max(_at(u, 0, pts), exact)
+    del u
+    u, _ = _plan_solve(wl)
+    err_64 = rel_max(_at(u, 0, pts), exact)
+    del u
+    torch.cuda.empty_cache()
+    u, _ = _plan_solve(wl, dtype="f32", f=wl["f"].astype(np.float32))
+    err_32 = rel_max(_at(u, 0, pts), exact)
+    banner(f"errors: refined {err_r:.2e}, f64 {err_64:.2e}, f32 {err_32:.2e}")
+    assert err_r < 1e-12 and err_64 < 1e-12 and err_32 < 1e-5
+
+
+def _c5_expected(wl, pts, b):
+    """Exact u and dJ/df = G^T (u - u_t) = G (u - u_t) (Dirichlet: symmetric) at sample points."""
+    modes, a = wl["modes"][b]
+    tmodes, t = wl["target_modes"][b]
+    shape, L = wl["shape"], wl["lengths"]
+    u = closed_form.solve_mode_sum_at(modes, a, shape, L, pts)
+    h = wl["h"]
+    lam = np.array([closed_form.eigenvalue(m["w"], h) for m in modes])
+    g = (closed_form.solve_mode_sum_at(modes, a / lam, shape, L, pts)
+         - closed_form.solve_mode_sum_at(tmodes, t, shape, L, pts))
+    return u, g
+
+
+def test_adjoint_ddd_384_batch4_gradient():
+    import torch
+    from gpu_util import banner, rel_max
+    from paper_1909_05423_amd import Plan, poisson_solve
+    banner("adjoint_ddd 384^3 x4: u, dJ/df via autograd, finite differences")
+    wl = workloads.make("adjoint_ddd")
+    plan = Plan(wl["shape"], wl["bc"], wl["h"], dtype="f64", batch=4)
+    f = torch.from_numpy(wl["f"]).to("cuda").requires_grad_(True)
+    ut = torch.from_numpy(wl["target"]).to("cuda")
+    u = poisson_solve(f, plan)
+    J = 0.5 * ((u - ut) ** 2).sum()
+    J.backward()
+    grad = f.grad.detach()
+    pts = _sample_points(wl["shape"], 2048, 51)
+    for b in range(4):
+        ue, ge = _c5_expected(wl, pts, b)
+        assert rel_max(_at(u.detach(), b, pts), ue) < 1e-12
+        assert rel_max(_at(grad, b, pts), ge) < 1e-12
+    # central finite differences along 3 random directions.  J is quadratic, so the
+    # central difference is exact for any step; J(f+ev) - J(f-ev) is formed point by
+    # point, (u+ - u-)(u+ + u- - 2 u_t)/2, before the sum, so the large J cancels
+    # exactly instead of in the rounded totals.
+    rng = np.random.default_rng(52)
+    fd0 = f.detach()
+    for k in range(3):
+        v = torch.from_numpy(rng.standard_normal(fd0.shape)).to("cuda")
+        eps = 1e-3 * float(fd0.abs().max() / v.abs().max())
+        with torch.no_grad():
+            up = plan.solve(fd0 + eps * v)
+            um = plan.solve(fd0 - eps * v)
+            fdv = float((0.5 * (up - um) * (up + um - 2.0 * ut)).sum() / (2 * eps))
+            an = float((grad * v).sum())
+        assert abs(fdv - an) <= 1e-6 * abs(an), (k, fdv, an)
+    # float adjoint against the double one
+    plan32 = Plan(wl["shape"], wl["bc"], wl["h"], dtype="f32", batch=4)
+    g32 = plan32.adjoint((u.detach() - ut).float())
+    assert float((g32.double() - grad).abs().max() / grad.abs().max()) < 1e-5
+
+
+@pytest.mark.parametrize("bc,gauge", [("DDDDDD", "mean"), ("PPPPNN", "mean"), ("NNPPNN", "pin"),
+                                      ("PPNNND", "mean"), ("NNNNNN", "pin_raw")])
+def test_dense_gradient_tiny(bc, gauge):
+    """dJ/df against the dense transposed solution operator on grids of at most 8^3."""
+    import torch
+    from gpu_util import rel_max
+    from oracle.dense import dense_operator
+    from paper_1909_05423_amd import Plan, poisson_solve
+    shape, h = (6, 8, 8), (0.3, 0.2, 0.5)
+    rng = np.random.default_rng(61)
+    fnp = rng.standard_normal((1,) + shape)
+    tnp = rng.standard_normal((1,) + shape)
+    G = dense_operator(shape, bc, h, gauge)
+    plan = Plan(shape, bc, h, gauge=gauge)
+    f = torch.from_numpy(fnp).to("cuda").requires_grad_(True)
+    u = poisson_solve(f, plan)
+    J = 0.5 * ((u - torch.from_numpy(tnp).to("cuda")) ** 2).sum()
+    J.backward()
+    ud = G @ fnp.reshape(-1)
+    gd = G.T @ (ud - tnp.reshape(-1))
+    assert rel_max(u.detach().cpu().numpy().reshape(-1), ud) < 1e-12
+    assert rel_max(f.grad.cpu().numpy().reshape(-1), gd) < 1e-12

@@ -1,0 +1,172 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element
+by element, on seeded inputs at sizes the oracle finishes in seconds.
+
+Tolerances (relative max-norm against the oracle): 1e-12 in double, 1e-5 for
+the unrefined float solve, 1e-12 for the refined float solve.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+BC_X = "PND"
+BC_Z = ["DD", "NN", "DN", "ND"]
+ALL_BCS = [x * 2 + y * 2 + z for x in BC_X for y in BC_X for z in BC_Z]
+
+# shapes (nz, ny, nx): several LDS tiles, ragged tails, odd and 2^a 3^b lengths, unit lengths
+SHAPES = [(7, 12, 16), (5, 9, 6), (3, 1, 4), (1, 4, 3), (2, 3, 1), (37, 36, 48), (20, 32, 27)]
+
+
+def _solve(f, bc, h, dtype="f64", gauge="mean", batch=None, adjoint=False, **kw):
+    import torch
+    from paper_1909_05423_amd import Plan
+    from gpu_util import to_dev
+    f = np.asarray(f)
+    if batch is None:
+        batch = 1 if f.ndim == 3 else f.shape[0]
+    plan = Plan(f.shape[-3:], bc, h, dtype=dtype, batch=batch, gauge=gauge, **kw)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    fd = to_dev(f.reshape((batch,) + f.shape[-3:]), tdt)
+    u = plan.adjoint(fd) if adjoint else plan.solve(fd)
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy().reshape(f.shape), plan
+
+
+@pytest.mark.parametrize("bc", ALL_BCS)
+def test_f64_all_bcs(bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(sum(map(ord, bc)))
+    for shape in SHAPES:
+        banner(f"f64 {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal(shape)
+        u, _ = _solve(f, bc, h)
+        uo = oracle.solve(f, bc, h, "mean")
+        assert rel_max(u, uo) < 1e-12, (bc, shape)
+
+
+@pytest.mark.parametrize("bc", ["PPPPDD", "DDNNNN", "PPPPNN", "NNNNNN", "DDDDDD", "NNPPDN", "PPNNND"])
+def test_f32_all_bcs(bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(7 + sum(map(ord, bc)))
+    for shape in SHAPES:
+        banner(f"f32 {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal(shape)
+        u, _ = _solve(f.astype(np.float32).astype(np.float64), bc, h, dtype="f32")
+        uo = oracle.solve(f.astype(np.float32).astype(np.float64), bc, h, "mean")
+        assert rel_max(u, uo) < 1e-5, (bc, shape)
+
+
+@pytest.mark.parametrize("bc", ["PPPPNN", "NNNNNN", "NNPPNN", "PPNNNN"])
+@pytest.mark.parametrize("gauge", ["mean", "pin", "pin_raw"])
+def test_gauges_singular(bc, gauge):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(11)
+    for shape in [(8, 12, 16), (5, 6, 9), (33, 18, 24)]:
+        banner(f"gauge {gauge} {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal(shape) + 0.3       # incompatible: non-zero mean
+        u, plan = _solve(f, bc, h, gauge=gauge)
+        uo = oracle.solve(f, bc, h, gauge)
+        assert rel_max(u, uo) < 1e-12
+        its, means, _ = plan.last_info()
+        expect = f.mean() if gauge != "pin_raw" else 0.0
+        assert abs(means[0] - expect) < 1e-13 * max(1.0, abs(f).max())
+
+
+@pytest.mark.parametrize("bc", ["PPPPDD", "DDNNNN", "PPPPNN", "NNNNNN", "NNPPDN"])
+@pytest.mark.parametrize("gauge", ["mean", "pin", "pin_raw"])
+def test_adjoint_against_oracle(bc, gauge):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(13)
+    for shape in [(8, 12, 16), (5, 9, 6), (20, 32, 27)]:
+        banner(f"adjoint {gauge} {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        g = rng.standard_normal(shape)
+        v, _ = _solve(g, bc, h, gauge=gauge, adjoint=True)
+        vo = oracle.solve_adjoint(g, bc, h, gauge)
+        assert rel_max(v, vo) < 1e-12
+
+
+@pytest.mark.parametrize("bc", ["PPPPDD", "DDNNNN", "PPPPNN", "NNPPDN"])
+def test_refined_matches_oracle(bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(17)
+    for shape in [(8, 12, 16), (37, 36, 48)]:
+        banner(f"refined {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal(shape)
+        u, plan = _solve(f, bc, h, dtype="f32_refined")
+        uo = oracle.solve(f, bc, h, "mean")
+        its, _, rel = plan.last_info()
+        assert 1 <= its <= 8
+        assert rel_max(u, uo) < 1e-12, (its, rel)
+
+
+def test_batched_equals_single():
+    from gpu_util import rel_max
+    rng = np.random.default_rng(19)
+    for bc in ["PPPPNN", "DDDDDD"]:
+        f = rng.standard_normal((3, 9, 12, 16))
+        h = (0.7, 1.1, 0.9)
+        ub, plan = _solve(f, bc, h, batch=3)
+        uo = oracle.solve(f, bc, h)
+        assert rel_max(ub, uo) < 1e-12
+        its, means, _ = plan.last_info()
+        if bc == "PPPPNN":
+            np.testing.assert_allclose(means, f.mean(axis=(1, 2, 3)), atol=1e-14)
+
+
+def test_nonfinite_source_reported():
+    import torch
+    from paper_1909_05423_amd import Plan, _lib
+    from gpu_util import to_dev
+    f = np.zeros((4, 6, 8))
+    f[1, 2, 3] = np.nan
+    plan = Plan((4, 6, 8), "PPPPNN", (1, 1, 1))
+    plan.solve(to_dev(f))
+    with pytest.raises(_lib.PPError) as ei:
+        plan.last_info()
+    assert ei.value.status == -8
+    torch.cuda.synchronize()
+
+
+def test_refinement_not_converged_reported():
+    from paper_1909_05423_amd import Plan, _lib
+    from gpu_util import to_dev
+    f = np.random.default_rng(3).standard_normal((6, 8, 12))
+    plan = Plan((6, 8, 12), "PPPPDD", (1, 1, 1), dtype="f32_refined", refine_max_iter=0)
+    with pytest.raises(_lib.PPError) as ei:
+        plan.solve(to_dev(f))
+    assert ei.value.status == -7
+
+
+def test_workspace_rebinding_and_reuse():
+    """Two plans, two workspaces, alternating calls: tables are bound per workspace."""
+    import torch
+    from paper_1909_05423_amd import Plan
+    from gpu_util import to_dev, rel_max
+    rng = np.random.default_rng(23)
+    f1 = rng.standard_normal((6, 8, 12))
+    f2 = rng.standard_normal((6, 8, 12))
+    p1 = Plan((6, 8, 12), "PPPPNN", (1, 1, 1))
+    p2 = Plan((6, 8, 12), "DDNNDD", (1, 1, 1))
+    for _ in range(2):
+        u1 = p1.solve(to_dev(f1))
+        u2 = p2.solve(to_dev(f2))
+    torch.cuda.synchronize()
+    assert rel_max(u1.cpu().numpy(), oracle.solve(f1, "PPPPNN", (1, 1, 1))) < 1e-12
+    assert rel_max(u2.cpu().numpy(), oracle.solve(f2, "DDNNDD", (1, 1, 1))) < 1e-12
+
+
+def test_mms_ppd_workload_small():
+    from gpu_util import rel_max
+    wl = workloads.make("mms_ppd")
+    u, _ = _solve(wl["f"], wl["bc"], wl["h"])
+    uo = oracle.solve(wl["f"], wl["bc"], wl["h"])
+    assert rel_max(u, uo) < 1e-12
