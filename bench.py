@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--workload", default="div_ppn")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-refined", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (torch copy_) three times, as the reference "
+                         "kernel of known size for hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -170,6 +173,15 @@ def main():
     f = torch.from_numpy(wl["f"]).to("cuda")
     f_host = wl.pop("f")
     u = torch.empty_like(f)
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies done")
+        del a, b
 
     log(f"plan f64 {shape} {bc} batch {batch}")
     plan = Plan(shape, bc, h, dtype="f64", batch=batch)

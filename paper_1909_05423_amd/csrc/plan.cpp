@@ -537,7 +537,7 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     if (code[0] != code[1] || code[2] != code[3]) return PP_ERR_BC;
     if (code[4] == pp::BC_P || code[5] == pp::BC_P) return PP_ERR_BC;
     if (!factor23(nx) || !factor23(ny)) return PP_ERR_SIZE;
-    if (nx > 2048 || ny > pp::kThreads * pp::kMaxOwned) return PP_ERR_SIZE;
+    if (nx > pp::kMaxLine || ny > pp::kMaxLine || ny > pp::kZThreads * pp::kZOwned) return PP_ERR_SIZE;
     if ((long long)nz * batch > 65535) return PP_ERR_SIZE;
 
     pp_plan p = new (std::nothrow) pp_plan_s;
@@ -561,9 +561,11 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     p->fy = radix_plan(ny);
     p->ldl = pp::padded_len(nx);
     p->ldy = pp::padded_len(ny);
-    const int cap = pp::kLdsBytes / (int)p->elem;
-    int lines = std::min(cap / p->ldl, (ny + 1) / 2);
-    p->zb = std::min(cap / p->ldy, nz);
+    int lines = std::min(pp::kXElems / nx, (ny + 1) / 2);
+    // z planes per chunk: the LDS holds zb lines of ny, and each thread carries
+    // zb * ceil(ny / kZThreads) values in registers
+    const int own = (ny + pp::kZThreads - 1) / pp::kZThreads;
+    p->zb = std::min({pp::kZElems / ny, pp::kEpt / own, nz});
     if (lines < 1 || p->zb < 1) {
         delete p;
         return PP_ERR_SIZE;

@@ -76,6 +76,11 @@ template <bool INV, typename V> __device__ __forceinline__ V rot(V a) {
     return r;
 }
 
+// floor(i / n) for 0 <= i, 1 <= n with i + n < 2^22, from inv = 1.0f / n:
+// (i + 1/2) / n lies at least 1/(2n) away from an integer, and the float
+// rounding error of (i + 1/2) * inv is below (i/n + 1) 2^-23 < 1/(2n).
+__device__ __forceinline__ int fdiv(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
+
 __host__ __device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
 __host__ __device__ constexpr int padded_len(int n) { return n + ((n - 1) >> 3); }
 
@@ -160,6 +165,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ldl, int nlines, int
     const int total = nlines * nbf;
     const int step = N / (Ls * R);
     const int tid = threadIdx.x;
+    const float inv_nbf = 1.0f / (float)nbf, inv_ls = 1.0f / (float)Ls;
     cplx<T> v[MAXB][R];
     int dline[MAXB], didx[MAXB];
 #pragma unroll
@@ -167,9 +173,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ldl, int nlines, int
         const int bidx = tid + i * NTH;
         dline[i] = -1;
         if (bidx < total) {
-            const int line = bidx / nbf;
+            const int line = fdiv(bidx, inv_nbf);
             const int j = bidx - line * nbf;
-            const int k = j % Ls;
+            const int k = j - fdiv(j, inv_ls) * Ls;
             const cplx<T>* src = buf + line * ldl;
 #pragma unroll
             for (int t = 0; t < R; ++t) v[i][t] = src[pad(j + t * nbf)];
@@ -196,18 +202,18 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ldl, int nlines, int
     __syncthreads();
 }
 
-// Transform `nlines` lines of d.n complex values in LDS, in place.  EMAX is the
-// LDS capacity in complex elements (nlines * d.n <= EMAX).  Callers synchronise
-// before the call; the call ends with a barrier.
-template <int NTH, int EMAX, bool INV, typename T>
+// Transform `nlines` lines of d.n complex values in LDS, in place, with NTH
+// threads owning at most EPT values each (nlines * d.n <= NTH * EPT).  Callers
+// synchronise before the call; the call ends with a barrier.
+template <int NTH, int EPT, bool INV, typename T>
 __device__ void fft_lines(cplx<T>* buf, int ldl, int nlines, const FftDesc& d, const cplx<T>* __restrict__ tw) {
     int Ls = 1;
     for (int s = 0; s < d.nstages; ++s) {
         const int R = d.radix[s];
-        if (R == 8) fft_stage<8, cdiv(EMAX, 8 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        else if (R == 4) fft_stage<4, cdiv(EMAX, 4 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        else if (R == 3) fft_stage<3, cdiv(EMAX, 3 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        else fft_stage<2, cdiv(EMAX, 2 * NTH), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        if (R == 8) fft_stage<8, cdiv(EPT, 8), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        else if (R == 4) fft_stage<4, cdiv(EPT, 4), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        else if (R == 3) fft_stage<3, cdiv(EPT, 3), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
+        else fft_stage<2, cdiv(EPT, 2), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
         Ls *= R;
     }
 }

@@ -11,20 +11,26 @@ namespace pp {
 
 enum Bc : int { BC_P = 0, BC_N = 1, BC_D = 2 };
 
-// LDS budget of one workgroup (bytes) and the threads of every transform kernel.
-constexpr int kLdsBytes = 73728;
-constexpr int kThreads = 256;
-// Entries (spectral y positions) one thread of the z-march owns: ny <= kThreads * kMaxOwned.
-constexpr int kMaxOwned = 8;
-
-template <typename T> constexpr int lds_elems() { return kLdsBytes / (int)sizeof(cplx<T>); }
+// Launch shapes.  Every transform kernel gives each thread at most kEpt
+// complex values of the lines it holds in LDS (FFT stages keep one radix-8
+// butterfly, two radix-4, three radix-3 or four radix-2 butterflies per thread
+// in registers).
+constexpr int kEpt = 8;
+constexpr int kXThreads = 256;                 // x kernels: lines of nx per workgroup = kXElems / nx
+constexpr int kXElems = kXThreads * kEpt;
+constexpr int kZThreads = 512;                 // z march: planes per chunk = kZElems / ny
+constexpr int kZElems = kZThreads * kEpt;
+// Entries (spectral y positions) one thread of the z march owns: ny <= kZThreads * kZOwned;
+// a chunk holds zb <= kEpt / ceil(ny / kZThreads) planes.
+constexpr int kZOwned = 4;
+constexpr int kMaxLine = 2048;                 // longest x or y line
 
 // x-direction kernels: a workgroup owns `ty` consecutive rows (y0 .. y0+ty-1)
 // of one z plane of one batch entry, packed two rows per complex line.
 template <typename T> struct XArgs {
     int nx, ny, nz, slots;   // slots = ceil(nx/2) spectral columns per row
     int bx;                  // boundary type along x (Bc)
-    int ty;                  // rows per workgroup (even)
+    int ty;                  // rows per workgroup (even; ty/2 * nx <= kXElems)
     int ldl;                 // LDS line stride (padded_len(nx))
     FftDesc fx;              // radix plan for nx
     const cplx<T>* twx;      // exp(-2 pi i j / nx), j < nx
@@ -39,7 +45,7 @@ template <typename T> struct MidArgs {
     int ny, nz, slots;
     int bx, by;
     int ldy;                 // LDS line stride (padded_len(ny))
-    int zb;                  // z planes per LDS chunk
+    int zb;                  // z planes per LDS chunk (zb * ny <= kZElems, zb * own <= kEpt)
     int singular;            // zero mode present (slot 0, entry 0, real part)
     int project;             // subtract the source mean from the zero-mode line
     int demean;              // report the mean of the zero-mode solution (subtracted by the x inverse)

@@ -27,23 +27,14 @@
 
 namespace pp {
 
+// One DCT-II bin of a packed pair of rows, from the DFT V of the reordered
+// complex line: C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}), V_N = V_0.
 template <typename T>
-__device__ __forceinline__ cplx<T> row_dft(const cplx<T>* line, int k, int part, int N) {
-    // DFT of row `part` of a packed pair from the DFT Z of the complex line:
-    //   X_a[k] = (Z_k + conj Z_{N-k}) / 2,  X_b[k] = (Z_k - conj Z_{N-k}) / (2i)
-    const cplx<T> zk = line[pad(k)];
-    const cplx<T> zr = line[pad(k == 0 ? 0 : N - k)];
-    if (part == 0) return mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
-    return mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
-}
-
-template <typename T>
-__device__ __forceinline__ T row_dct(const cplx<T>* line, const cplx<T>* __restrict__ mkt, int k, int part, int N) {
+__device__ __forceinline__ cplx<T> dct_bin(const cplx<T>* line, const cplx<T>* __restrict__ mkt, int k, int N) {
     const cplx<T> vk = line[pad(k)];
     const cplx<T> vr = line[pad(k == 0 ? 0 : N - k)];
     const cplx<T> w = mkt[k];
-    const cplx<T> c = cadd(cmul(w, vk), cmulc(vr, w));   // e^{-} V_k + e^{+} V_{N-k}
-    return T(0.5) * (part == 0 ? c.x : c.y);
+    return cscale(cadd(cmul(w, vk), cmulc(vr, w)), T(0.5));
 }
 
 template <typename T, typename Tin, int NTH>
@@ -57,25 +48,36 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
     const int tid = threadIdx.x;
     const Tin* src = f + ((size_t)b * nz + z) * (size_t)ny * nx;
 
-    // 1. rows -> packed complex lines, pre-processed for the x transform
+    // 1. rows -> packed complex lines (row 2j real part, row 2j+1 imaginary part),
+    //    pre-processed for the x transform
     double acc = 0.0, amax = 0.0;
-    for (int i = tid; i < ty * nx; i += NTH) {
-        const int r = i / nx, n = i - r * nx;
-        const int y = y0 + r;
-        T v = T(0);
-        if (y < ny) {
-            const Tin raw = src[(size_t)y * nx + n];
+    const int nlines = ty >> 1;
+    const float inv_nx = 1.0f / (float)nx, inv_nl = 1.0f / (float)nlines;
+    for (int i = tid; i < nlines * nx; i += NTH) {
+        const int j = fdiv(i, inv_nx), n = i - j * nx;
+        const int ya = y0 + 2 * j, yb = ya + 1;
+        T va = T(0), vb = T(0);
+        if (ya < ny) {
+            const Tin raw = src[(size_t)ya * nx + n];
             acc += (double)raw;
             amax = fmax(amax, fabs((double)raw));
-            v = (T)raw;
+            va = (T)raw;
+        }
+        if (yb < ny) {
+            const Tin raw = src[(size_t)yb * nx + n];
+            acc += (double)raw;
+            amax = fmax(amax, fabs((double)raw));
+            vb = (T)raw;
         }
         int pos = n;
         if (a.bx != BC_P) {
             pos = makhoul_pos(n, nx);
-            if (a.bx == BC_D && (n & 1)) v = -v;
+            if (a.bx == BC_D && (n & 1)) {
+                va = -va;
+                vb = -vb;
+            }
         }
-        T* dst = reinterpret_cast<T*>(lds + (r >> 1) * ldl + pad(pos)) + (r & 1);
-        *dst = v;
+        lds[j * ldl + pad(pos)] = mk<T>(va, vb);
     }
     const double bsum = block_sum<NTH>(acc, red);
     const double bmax = block_max<NTH>(amax, red);
@@ -87,33 +89,40 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
     __syncthreads();
 
     // 2. complex FFT of every line
-    fft_lines<NTH, lds_elems<T>(), false, T>(lds, ldl, ty >> 1, a.fx, a.twx);
+    fft_lines<NTH, kEpt, false, T>(lds, ldl, ty >> 1, a.fx, a.twx);
 
-    // 3. post-process and write columns (y contiguous)
+    // 3. post-process and write columns (y contiguous); one thread per (slot, row pair)
     cplx<T>* dstS = S + (size_t)b * a.slots * nz * ny;
-    const int nslot = a.slots;
-    for (int i = tid; i < nslot * ty; i += NTH) {
-        const int m = i / ty, r = i - m * ty;
-        const int y = y0 + r;
-        if (y >= ny) continue;
-        const cplx<T>* line = lds + (r >> 1) * ldl;
-        const int part = r & 1;
-        cplx<T> out;
+    for (int i = tid; i < a.slots * nlines; i += NTH) {
+        const int m = fdiv(i, inv_nl), j = i - m * nlines;
+        const int ya = y0 + 2 * j, yb = ya + 1;
+        const cplx<T>* line = lds + j * ldl;
+        cplx<T> oa, ob;
         if (a.bx == BC_P) {
             if (m == 0) {
-                const T x0 = row_dft<T>(line, 0, part, nx).x;
-                const T xn = (nx & 1) ? T(0) : row_dft<T>(line, nx >> 1, part, nx).x;
-                out = mk<T>(x0, xn);
+                const cplx<T> z0 = line[pad(0)];
+                // X_a[0] = Re Z_0, X_b[0] = Im Z_0; likewise at the Nyquist bin
+                cplx<T> zn = mk<T>(T(0), T(0));
+                if (!(nx & 1)) zn = line[pad(nx >> 1)];
+                oa = mk<T>(z0.x, zn.x);
+                ob = mk<T>(z0.y, zn.y);
             } else {
-                out = row_dft<T>(line, m, part, nx);
+                // X_a[m] = (Z_m + conj Z_{N-m}) / 2,  X_b[m] = (Z_m - conj Z_{N-m}) / (2i)
+                const cplx<T> zk = line[pad(m)], zr = line[pad(nx - m)];
+                oa = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                ob = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
             }
         } else {
+            // C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}); real part -> row a, imaginary -> row b
             const int k0 = 2 * m, k1 = 2 * m + 1;
-            const T c0 = row_dct<T>(line, a.mkx, k0, part, nx);
-            const T c1 = (k1 < nx) ? row_dct<T>(line, a.mkx, k1, part, nx) : T(0);
-            out = mk<T>(c0, c1);
+            const cplx<T> c0 = dct_bin<T>(line, a.mkx, k0, nx);
+            const cplx<T> c1 = (k1 < nx) ? dct_bin<T>(line, a.mkx, k1, nx) : mk<T>(T(0), T(0));
+            oa = mk<T>(c0.x, c1.x);
+            ob = mk<T>(c0.y, c1.y);
         }
-        dstS[((size_t)m * nz + z) * ny + y] = out;
+        const size_t col = ((size_t)m * nz + z) * ny;
+        if (ya < ny) dstS[col + ya] = oa;
+        if (yb < ny) dstS[col + yb] = ob;
     }
 }
 
@@ -137,10 +146,11 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     const int tid = threadIdx.x;
     const int nlines = ty >> 1;
     const cplx<T>* srcS = S + (size_t)b * a.slots * nz * ny;
+    const float inv_nl = 1.0f / (float)nlines, inv_nx = 1.0f / (float)nx;
 
     // 1. columns -> packed complex spectra of row pairs
     for (int i = tid; i < a.slots * nlines; i += NTH) {
-        const int m = i / nlines, j = i - m * nlines;
+        const int m = fdiv(i, inv_nl), j = i - m * nlines;
         const int ya = y0 + 2 * j, yb = ya + 1;
         const size_t col = ((size_t)m * nz + z) * ny;
         const cplx<T> sa = (ya < ny) ? srcS[col + ya] : mk<T>(T(0), T(0));
@@ -162,8 +172,9 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     __syncthreads();
     if (a.bx != BC_P) {
         const int half = (nx >> 1) + 1;
+        const float inv_half = 1.0f / (float)half;
         for (int i = tid; i < nlines * half; i += NTH) {
-            const int j = i / half, k = i - j * half;
+            const int j = fdiv(i, inv_half), k = i - j * half;
             if (k == 0) continue;                       // W_0 = X_0
             cplx<T>* line = lds + j * ldl;
             const cplx<T> xk = line[pad(k)];
@@ -180,7 +191,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     }
 
     // 2. inverse complex FFT (unnormalised)
-    fft_lines<NTH, lds_elems<T>(), true, T>(lds, ldl, nlines, a.fx, a.twx);
+    fft_lines<NTH, kEpt, true, T>(lds, ldl, nlines, a.fx, a.twx);
 
     // 3. rows out
     const double sh = shift ? shift[b] : 0.0;
@@ -191,25 +202,28 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     }
     double acc = 0.0, dmax = 0.0, umax = 0.0;
     Tout* dst = u + ((size_t)b * nz + z) * (size_t)ny * nx;
-    for (int i = tid; i < ty * nx; i += NTH) {
-        const int r = i / nx, n = i - r * nx;
-        const int y = y0 + r;
-        if (y >= ny) continue;
+    for (int i = tid; i < nlines * nx; i += NTH) {
+        const int j = fdiv(i, inv_nx), n = i - j * nx;
         int pos = n;
         if (a.bx != BC_P) pos = makhoul_pos(n, nx);
-        const cplx<T> c = lds[(r >> 1) * ldl + pad(pos)];
-        T v = (r & 1) ? c.y : c.x;
-        if (a.bx == BC_D && (n & 1)) v = -v;
-        const size_t idx = (size_t)y * nx + n;
-        if (MODE == XINV_STORE) {
-            dst[idx] = (Tout)((double)v - sh);
-        } else {
-            const double d = ((double)v - sh) * inv_scale;
-            const double un = (double)dst[idx] + d - gshift;
-            dst[idx] = (Tout)un;
-            if (gauge_region == 1 || (gauge_region == 2 && z == 0)) acc += un;
-            dmax = fmax(dmax, fabs(d));
-            umax = fmax(umax, fabs(un));
+        cplx<T> c = lds[j * ldl + pad(pos)];
+        if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+            const int y = y0 + 2 * j + part;
+            if (y >= ny) continue;
+            const T v = part ? c.y : c.x;
+            const size_t idx = (size_t)y * nx + n;
+            if (MODE == XINV_STORE) {
+                dst[idx] = (Tout)((double)v - sh);
+            } else {
+                const double d = ((double)v - sh) * inv_scale;
+                const double un = (double)dst[idx] + d - gshift;
+                dst[idx] = (Tout)un;
+                if (gauge_region == 1 || (gauge_region == 2 && z == 0)) acc += un;
+                dmax = fmax(dmax, fabs(d));
+                umax = fmax(umax, fabs(un));
+            }
         }
     }
     if (MODE == XINV_UPDATE) {
@@ -234,7 +248,7 @@ template <typename K> static void allow_lds(K kernel) {
     static bool done = false;
     if (!done) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kLdsBytes);
+                                  (int)((kXElems + kXElems / 8) * sizeof(cplx<double>)));
         done = true;
     }
 }
@@ -242,16 +256,16 @@ template <typename K> static void allow_lds(K kernel) {
 template <typename T, typename Tin>
 hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch, hipStream_t s) {
     dim3 grid((a.ny + a.ty - 1) / a.ty, a.nz, batch);
-    allow_lds(k_xfwd<T, Tin, kThreads>);
-    hipLaunchKernelGGL((k_xfwd<T, Tin, kThreads>), grid, dim3(kThreads), x_lds_bytes(a), s, f, S, partial, a);
+    allow_lds(k_xfwd<T, Tin, kXThreads>);
+    hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads>), grid, dim3(kXThreads), x_lds_bytes(a), s, f, S, partial, a);
     return hipGetLastError();
 }
 
 template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift, hipStream_t s) {
     dim3 grid((a.ny + a.ty - 1) / a.ty, a.nz, batch);
-    allow_lds(k_xinv<T, Tout, kThreads, XINV_STORE>);
-    hipLaunchKernelGGL((k_xinv<T, Tout, kThreads, XINV_STORE>), grid, dim3(kThreads), x_lds_bytes(a), s, S, u, a,
+    allow_lds(k_xinv<T, Tout, kXThreads, XINV_STORE>);
+    hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, XINV_STORE>), grid, dim3(kXThreads), x_lds_bytes(a), s, S, u, a,
                        shift, (const double*)nullptr, 0, (double*)nullptr);
     return hipGetLastError();
 }
@@ -260,8 +274,8 @@ hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float
                               const double* scalars, int gauge_region, double* partial, hipStream_t s) {
     dim3 grid((a.ny + a.ty - 1) / a.ty, a.nz, batch);
     const double* shift = scalars + SC_COUNT + batch;   // cmean of the correction solve
-    allow_lds(k_xinv<float, double, kThreads, XINV_UPDATE>);
-    hipLaunchKernelGGL((k_xinv<float, double, kThreads, XINV_UPDATE>), grid, dim3(kThreads), x_lds_bytes(a), s, S, u,
+    allow_lds(k_xinv<float, double, kXThreads, XINV_UPDATE>);
+    hipLaunchKernelGGL((k_xinv<float, double, kXThreads, XINV_UPDATE>), grid, dim3(kXThreads), x_lds_bytes(a), s, S, u,
                        a, shift, scalars, gauge_region, partial);
     return hipGetLastError();
 }
