@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--workload", default="div_ppn")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-refined", action="store_true")
+    ap.add_argument("--skip-check", action="store_true", help="skip the host-side backward-error check")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) three times, as the reference "
                          "kernel of known size for hardware traffic counters")
@@ -216,12 +217,13 @@ def main():
     }
 
     # correctness of the timed result (outside the timed region): normwise backward error
-    import oracle
-    u64 = u.cpu().numpy()
-    fp = f_host - f_host.mean(axis=(1, 2, 3), keepdims=True) if oracle.is_singular(bc) else f_host
-    eta = max(oracle.backward_error(fp[b], u64[b], bc, h) for b in range(batch))
-    result["f64_backward_error"] = float(eta)
-    log(f"f64 backward error {eta:.2e}")
+    if not args.skip_check:
+        import oracle
+        u64 = u.cpu().numpy()
+        fp = f_host - f_host.mean(axis=(1, 2, 3), keepdims=True) if oracle.is_singular(bc) else f_host
+        eta = max(oracle.backward_error(fp[b], u64[b], bc, h) for b in range(batch))
+        result["f64_backward_error"] = float(eta)
+        log(f"f64 backward error {eta:.2e}")
 
     if not args.skip_refined:
         plan_r = Plan(shape, bc, h, dtype="f32_refined", batch=batch)

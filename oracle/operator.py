@@ -10,28 +10,42 @@ Stencil (Eq. 3):  sum_d (u_{+1} - 2 u + u_{-1}) / h_d^2 = f.
 
 Ghost rules at a face (section "Boundary Conditions"):
   'P'  periodic: the ghost is the cell at the opposite end of the line.
-  'D'  homogeneous Dirichlet, value zero on the face: the ghost follows from
-       linear extrapolation through the face, u_ghost = -u_boundary_cell.
-  'N'  homogeneous Neumann, zero flux through the face: u_ghost = u_boundary_cell.
+  'D'  Dirichlet, value g on the face: the ghost follows from linear
+       extrapolation through the face (Dirichlet subsection),
+       u_ghost = 2 g - u_boundary_cell  (homogeneous: g = 0).
+  'N'  Neumann, outward normal derivative g on the face:
+       u_ghost = u_boundary_cell + h g  (homogeneous: g = 0, zero flux).
+
+Face values, when given, are a sequence of six arrays (or None for zero) in
+the face order (x-, x+, y-, y+, z-, z+): x faces have shape (..., nz, ny),
+y faces (..., nz, nx), z faces (..., ny, nx).
 """
 
 import numpy as np
 
 
-def _ghost(cell, kind, opposite):
+def _ghost(cell, kind, opposite, value=None, h=None):
     if kind == "P":
         return opposite
     if kind == "D":
-        return -cell
+        return -cell if value is None else 2.0 * value - cell
     if kind == "N":
-        return cell
+        return cell if value is None else cell + h * value
     raise ValueError(f"unknown boundary type {kind!r}")
 
 
-def apply_laplacian(u, bc, h):
+def _face(faces, i, axis):
+    """Face array i expanded with a unit axis in the position of its normal."""
+    if faces is None or faces[i] is None:
+        return None
+    return np.expand_dims(np.asarray(faces[i], dtype=np.float64), axis)
+
+
+def apply_laplacian(u, bc, h, faces=None):
     """Apply L_h (Eq. 3 with the ghost rules) to u of shape (..., nz, ny, nx).
 
-    bc is a 6-character string (x-, x+, y-, y+, z-, z+); h = (hx, hy, hz).
+    bc is a 6-character string (x-, x+, y-, y+, z-, z+); h = (hx, hy, hz);
+    faces (optional) holds the face values of non-homogeneous D/N faces.
     """
     u = np.asarray(u)
     out = np.zeros_like(u)
@@ -40,8 +54,8 @@ def apply_laplacian(u, bc, h):
         lo_kind, hi_kind = bc[2 * d], bc[2 * d + 1]
         first = np.take(u, [0], axis=axis)
         last = np.take(u, [u.shape[axis] - 1], axis=axis)
-        g_lo = _ghost(first, lo_kind, last)
-        g_hi = _ghost(last, hi_kind, first)
+        g_lo = _ghost(first, lo_kind, last, _face(faces, 2 * d, axis), h[d])
+        g_hi = _ghost(last, hi_kind, first, _face(faces, 2 * d + 1, axis), h[d])
         padded = np.concatenate([g_lo, u, g_hi], axis=axis)
         n = u.shape[axis]
         up = np.take(padded, np.arange(2, n + 2), axis=axis)
@@ -97,12 +111,19 @@ def operator_inf_norm(h):
     return sum(4.0 / (hd * hd) for hd in h)
 
 
-def backward_error(f, u, bc, h):
+def boundary_lift(shape, bc, h, faces):
+    """The affine part of L_h under non-homogeneous faces: L_h(0) with the given
+    face values (non-zero only in boundary cells).  L_h u = A u + lift, so the
+    face values move to the right-hand side as f - lift."""
+    return apply_laplacian(np.zeros(shape), bc, h, faces)
+
+
+def backward_error(f, u, bc, h, faces=None):
     """Normwise backward error  ||f - L_h u||_inf / (||L_h||_inf ||u||_inf + ||f||_inf).
 
     Pass the right-hand side the solution was meant to satisfy (in the singular
     case with projection, the projected source).
     """
-    r = np.asarray(f) - apply_laplacian(u, bc, h)
+    r = np.asarray(f) - apply_laplacian(u, bc, h, faces)
     den = operator_inf_norm(h) * np.max(np.abs(u)) + np.max(np.abs(f))
     return float(np.max(np.abs(r)) / den) if den > 0 else 0.0

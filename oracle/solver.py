@@ -134,10 +134,21 @@ def _mean(v):
     return v.mean(axis=(-3, -2, -1), keepdims=True)
 
 
-def solve(f, bc, h, gauge="mean"):
-    """Exact discrete solution of L_h u = f (see module docstring); f: (..., nz, ny, nx)."""
+def solve(f, bc, h, gauge="mean", faces=None):
+    """Exact discrete solution of L_h u = f (see module docstring); f: (..., nz, ny, nx).
+
+    faces: optional non-homogeneous face values (see operator.py).  Their ghost
+    contributions move to the right-hand side (Dirichlet subsection: "moved to
+    the right hand side"), f <- f - L_h(0), and the homogeneous problem is solved.
+    """
     f = _check(f, bc, h, gauge)
     nz, ny, nx = f.shape[-3:]
+    if faces is not None:
+        from .operator import boundary_lift
+        for i, kind in enumerate(bc):
+            if kind == "P" and faces[i] is not None:
+                raise ValueError("periodic faces carry no values")
+        f = f - boundary_lift(f.shape, bc, h, faces)
     singular = is_singular(bc)
     if singular and gauge in ("mean", "pin"):
         f = f - _mean(f)

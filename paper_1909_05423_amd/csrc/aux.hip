@@ -103,35 +103,57 @@ __device__ __forceinline__ double ghost_or(const double* p, long stride, int idx
     return kind == BC_D ? -self : self;
 }
 
+// One thread per (x, y) column and a stretch of kResZ planes: the z neighbours
+// come from a three-plane window in registers, the x and y neighbours from the
+// caches (their lines are loaded by the neighbouring threads of the block).
+constexpr int kResZ = 16;
+
+__device__ __forceinline__ double z_ghost(double cell, double opposite, int kind) {
+    if (kind == BC_P) return opposite;
+    return kind == BC_D ? -cell : cell;
+}
+
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, const double* __restrict__ u,
                                                   float* __restrict__ r, ResidualArgs a,
                                                   const double* __restrict__ sc) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     const int j = blockIdx.y * 4 + threadIdx.y;
-    const int kb = blockIdx.z;
+    const int nzc = (a.nz + kResZ - 1) / kResZ;
+    const int b = blockIdx.z / nzc;
+    const int z0 = (blockIdx.z - b * nzc) * kResZ;
     if (i >= a.nx || j >= a.ny) return;
-    const int k = kb % a.nz;
-    const size_t idx = (((size_t)kb) * a.ny + j) * a.nx + i;
-    const double* p = u + idx;
-    const double c = *p;
-    const double lx = ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], -1, c) + ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], 1, c);
-    const double ly = ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], -1, c) +
-                      ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], 1, c);
-    const long sz = (long)a.nx * a.ny;
-    const double lz = ghost_or(p, sz, k, a.nz, a.bc[4], a.bc[5], -1, c) + ghost_or(p, sz, k, a.nz, a.bc[4], a.bc[5], 1, c);
-    const double lap = (lx - 2.0 * c) * a.ihx2 + (ly - 2.0 * c) * a.ihy2 + (lz - 2.0 * c) * a.ihz2;
-    double fi = f[idx];
-    if (a.proj) {
-        const double mu = sc[SC_COUNT + 3 * a.batch + kb / a.nz];
+    const int z1 = min(z0 + kResZ, a.nz);
+    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t base = (size_t)b * a.nz * plane + (size_t)j * a.nx + i;
+    const double* ub = u + base;
+    const double mu = a.proj ? sc[SC_COUNT + 3 * a.batch + b] : 0.0;
+    const double scale = sc[SC_SCALE];
+    // window: below, centre, above
+    double uc = ub[(size_t)z0 * plane];
+    double ud = (z0 > 0) ? ub[(size_t)(z0 - 1) * plane]
+                         : z_ghost(uc, ub[(size_t)(a.nz - 1) * plane], a.bc[4]);
+    for (int k = z0; k < z1; ++k) {
+        const double* p = ub + (size_t)k * plane;
+        const double uu = (k + 1 < a.nz) ? p[plane] : z_ghost(uc, ub[0], a.bc[5]);
+        const double lx = ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], -1, uc) +
+                          ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], 1, uc);
+        const double ly = ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], -1, uc) +
+                          ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], 1, uc);
+        const double lap = (lx - 2.0 * uc) * a.ihx2 + (ly - 2.0 * uc) * a.ihy2 + (ud + uu - 2.0 * uc) * a.ihz2;
+        const size_t idx = base + (size_t)k * plane;
+        double fi = f[idx];
         if (a.proj == 1) fi -= mu;
-        else if (k == 0) fi -= (double)a.nz * mu;
+        else if (a.proj == 2 && k == 0) fi -= (double)a.nz * mu;
+        r[idx] = (float)((fi - lap) * scale);
+        ud = uc;
+        uc = uu;
     }
-    r[idx] = (float)((fi - lap) * sc[SC_SCALE]);
 }
 
 hipError_t launch_residual(const double* f, const double* u, float* r, const ResidualArgs& a, const double* scalars,
                            hipStream_t s) {
-    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz * a.batch);
+    const int nzc = (a.nz + kResZ - 1) / kResZ;
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, nzc * a.batch);
     hipLaunchKernelGGL(k_residual, grid, dim3(64, 4), 0, s, f, u, r, a, scalars);
     return hipGetLastError();
 }

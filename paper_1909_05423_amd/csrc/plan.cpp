@@ -426,7 +426,6 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     pp_status st;
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_ir_init(sc, p->batch, s));
-    PP_HIP(hipMemsetAsync(u, 0, sizeof(double) * n * p->batch, s));
     if ((st = mark(p, s, 0)) != PP_OK) return st;
     PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
@@ -436,7 +435,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
     ma.mu = sc + pp::SC_COUNT;   // corrections project their own right-hand side
     if ((st = mark(p, s, 2)) != PP_OK) return st;
-    PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, s));
+    PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 0, s));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_finalize_update(partial, (int)p->nper, p->batch, nregion, sc, 1, s));
     if ((st = mark(p, s, -1)) != PP_OK) return st;
@@ -452,7 +451,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         if ((st = mark(p, s, 1)) != PP_OK) return st;
         PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
         if ((st = mark(p, s, 2)) != PP_OK) return st;
-        PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, s));
+        PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 1, s));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
         PP_HIP(pp::launch_finalize_update(partial, (int)p->nper, p->batch, nregion, sc, 0, s));
         if ((st = mark(p, s, -1)) != PP_OK) return st;
@@ -561,17 +560,35 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     p->fy = radix_plan(ny);
     p->ldl = pp::padded_len(nx);
     p->ldy = pp::padded_len(ny);
-    int lines = std::min(pp::kXElems / nx, (ny + 1) / 2);
-    // z planes per chunk: the LDS holds zb lines of ny, and each thread carries
-    // zb * ceil(ny / kZThreads) values in registers
-    const int own = (ny + pp::kZThreads - 1) / pp::kZThreads;
-    p->zb = std::min({pp::kZElems / ny, pp::kEpt / own, nz});
+    // row pairs (lines) per x workgroup: each wavefront transforms lpw whole lines
+    // (64 * rmax >= lpw * nx values); capped by the rows present
+    int lines;
+    {
+        const int epl = (nx + 63) / 64;
+        const int lpw = std::max(1, pp::xdir_rmax(nx) / epl);
+        lines = std::min(pp::kXWaves * lpw, (ny + 1) / 2);
+        // the inverse gathers slots * lines (slot, row pair) values, rmax/2 per thread
+        while (lines > 1 && (size_t)((nx + 1) / 2) * lines > (size_t)pp::kXThreads * (pp::xdir_rmax(nx) / 2)) --lines;
+        const size_t xlds = ((size_t)lines * pp::padded_len(nx) + nx) * p->elem;
+        if (xlds > (size_t)pp::kXLdsBytes) lines = 0;
+    }
+    // z planes per chunk: each wavefront of the z march transforms whole planes,
+    // ppw = rmax / ceil(ny/64) of them per chunk; the LDS holds the chunk and the twiddles
+    {
+        const int nw = pp::kZThreads / 64;
+        const int epl = (ny + 63) / 64;
+        const int ppw = pp::zmarch_rmax(ny) / epl;
+        const int ldy = pp::padded_len(ny);
+        const int zb_lds = (int)((pp::kZLdsBytes / p->elem - (size_t)ny) / (size_t)ldy);
+        p->zb = std::min({nw * ppw, nz, zb_lds});
+    }
     if (lines < 1 || p->zb < 1) {
         delete p;
         return PP_ERR_SIZE;
     }
     p->ty = 2 * lines;
-    p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz;
+    // per-batch partial records: one per wavefront of every x-kernel row block
+    p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz * pp::kXWaves;
     if (f64) build_tables<double>(p);
     else build_tables<float>(p);
 

@@ -218,6 +218,123 @@ __device__ void fft_lines(cplx<T>* buf, int ldl, int nlines, const FftDesc& d, c
     }
 }
 
+// Ping-pong variant of a Stockham stage: reads `src`, writes `dst`, one
+// barrier; each butterfly goes straight from its loads to its stores, so only
+// one butterfly is live per thread at a time.
+template <int R, int NTH, bool INV, typename T>
+__device__ __forceinline__ void fft_stage_pp(const cplx<T>* src, cplx<T>* dst, int ldl, int nlines, int N, int Ls,
+                                             const cplx<T>* tw) {
+    const int nbf = N / R;
+    const int total = nlines * nbf;
+    const int step = N / (Ls * R);
+    const float inv_nbf = 1.0f / (float)nbf, inv_ls = 1.0f / (float)Ls;
+    for (int bidx = threadIdx.x; bidx < total; bidx += NTH) {
+        const int line = fdiv(bidx, inv_nbf);
+        const int j = bidx - line * nbf;
+        const int k = j - fdiv(j, inv_ls) * Ls;
+        const cplx<T>* s = src + line * ldl;
+        cplx<T> v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[t] = s[pad(j + t * nbf)];
+        if (Ls > 1) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                const cplx<T> w = tw[t * k * step];
+                v[t] = INV ? cmulc(v[t], w) : cmul(v[t], w);
+            }
+        }
+        bfly<R, INV, T>(v);
+        cplx<T>* d = dst + line * ldl;
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int t = 0; t < R; ++t) d[pad(base + t * Ls)] = v[t];
+    }
+    __syncthreads();
+}
+
+// Transform lines held in buffer a (b is scratch of the same shape); returns
+// the buffer that holds the result.  Callers synchronise before the call; the
+// call ends with a barrier.  `tw` may point to LDS or global memory.
+template <int NTH, bool INV, typename T>
+__device__ cplx<T>* fft_lines_pp(cplx<T>* a, cplx<T>* b, int ldl, int nlines, const FftDesc& d, const cplx<T>* tw) {
+    int Ls = 1;
+    for (int s = 0; s < d.nstages; ++s) {
+        const int R = d.radix[s];
+        if (R == 8) fft_stage_pp<8, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
+        else if (R == 4) fft_stage_pp<4, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
+        else if (R == 3) fft_stage_pp<3, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
+        else fft_stage_pp<2, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
+        Ls *= R;
+        cplx<T>* t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Order this wavefront's LDS accesses: LDS instructions of one wavefront are
+// performed in issue order, so a compiler-level fence at wavefront scope is
+// all a wave needs between writing and re-reading its own LDS region.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wavefront-private Stockham stage: the 64 lanes of one wave transform one
+// line in place (all of the wave's reads precede its writes in program order).
+// MAXB = butterflies per lane = ceil(N / R / 64).
+template <int R, int MAXB, bool INV, typename T>
+__device__ __forceinline__ void wfft_stage(cplx<T>* line, int N, int Ls, const cplx<T>* tw, int lane) {
+    const int nbf = N / R;
+    const int step = N / (Ls * R);
+    const float inv_ls = 1.0f / (float)Ls;
+    cplx<T> v[MAXB][R];
+    int dst[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int j = lane + 64 * i;
+        dst[i] = -1;
+        if (j < nbf) {
+            const int k = j - fdiv(j, inv_ls) * Ls;
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[i][t] = line[pad(j + t * nbf)];
+            if (Ls > 1) {
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    const cplx<T> w = tw[t * k * step];
+                    v[i][t] = INV ? cmulc(v[i][t], w) : cmul(v[i][t], w);
+                }
+            }
+            bfly<R, INV, T>(v[i]);
+            dst[i] = (j - k) * R + k;
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        if (dst[i] >= 0) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) line[pad(dst[i] + t * Ls)] = v[i][t];
+        }
+    }
+    wave_lds_sync();
+}
+
+// One line of d.n <= 64 * EPL complex values, transformed by one wavefront.
+template <int EPL, bool INV, typename T>
+__device__ __forceinline__ void wfft(cplx<T>* line, const FftDesc& d, const cplx<T>* tw, int lane) {
+    int Ls = 1;
+    for (int s = 0; s < d.nstages; ++s) {
+        const int R = d.radix[s];
+        if (R == 8) wfft_stage<8, cdiv(EPL, 8), INV, T>(line, d.n, Ls, tw, lane);
+        else if (R == 4) wfft_stage<4, cdiv(EPL, 4), INV, T>(line, d.n, Ls, tw, lane);
+        else if (R == 3) wfft_stage<3, cdiv(EPL, 3), INV, T>(line, d.n, Ls, tw, lane);
+        else wfft_stage<2, cdiv(EPL, 2), INV, T>(line, d.n, Ls, tw, lane);
+        Ls *= R;
+    }
+}
+
 // Sum of a double over the block (wave64 shuffles, then LDS across waves).
 // Result valid in thread 0.
 template <int NTH> __device__ __forceinline__ double block_sum(double v, double* red) {

@@ -18,12 +18,24 @@ enum Bc : int { BC_P = 0, BC_N = 1, BC_D = 2 };
 constexpr int kEpt = 8;
 constexpr int kXThreads = 256;                 // x kernels: lines of nx per workgroup = kXElems / nx
 constexpr int kXElems = kXThreads * kEpt;
+constexpr int kXBlocksPerCU = 2;               // persistent x-kernel workgroups per CU (all resident)
+constexpr int kXWaves = kXThreads / 64;
+constexpr int kXLdsBytes = 96 * 1024;          // x-kernel LDS ceiling (lines + twiddles)
+// x-kernel register shape: values per lane of one line (64 * RMAX >= nx).
+constexpr int xdir_rmax(int nx) { return nx <= 512 ? 8 : (nx <= 1024 ? 16 : 32); }
 constexpr int kZThreads = 512;                 // z march: planes per chunk = kZElems / ny
 constexpr int kZElems = kZThreads * kEpt;
 // Entries (spectral y positions) one thread of the z march owns: ny <= kZThreads * kZOwned;
 // a chunk holds zb <= kEpt / ceil(ny / kZThreads) planes.
 constexpr int kZOwned = 4;
 constexpr int kMaxLine = 2048;                 // longest x or y line
+// z-march LDS budget: zb padded lines plus ny twiddles.
+constexpr int kZLdsBytes = 160 * 1024 - 1024;
+constexpr size_t zmarch_lds_bytes(int zb, int ldy, int ny, size_t elem) {
+    return ((size_t)zb * ldy + (size_t)ny) * elem;
+}
+// z-march register shape: values per lane of a chunk (64 * RMAX >= ny).
+constexpr int zmarch_rmax(int ny) { return ny <= 512 ? 8 : (ny <= 1024 ? 16 : 32); }
 
 // x-direction kernels: a workgroup owns `ty` consecutive rows (y0 .. y0+ty-1)
 // of one z plane of one batch entry, packed two rows per complex line.
@@ -82,10 +94,12 @@ template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
                        hipStream_t s);
 
-// Refinement update: u += d / scale - gauge_shift[b]; partials (sum over the
-// gauge region of the new u, max |d / scale|, max |u_new|) per workgroup.
+// Refinement update: u = (accumulate ? u : 0) + d / scale - gauge_shift[b];
+// partials (sum over the gauge region of the new u, max |d / scale|, max |u_new|)
+// per wavefront.
 hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float>& a, int batch,
-                              const double* scalars, int gauge_region, double* partial, hipStream_t s);
+                              const double* scalars, int gauge_region, double* partial, int accumulate,
+                              hipStream_t s);
 
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);

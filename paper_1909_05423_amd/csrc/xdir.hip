@@ -37,247 +37,374 @@ __device__ __forceinline__ cplx<T> dct_bin(const cplx<T>* line, const cplx<T>* _
     return cscale(cadd(cmul(w, vk), cmulc(vr, w)), T(0.5));
 }
 
-template <typename T, typename Tin, int NTH>
+// Block index -> (row block, z plane, batch entry) of the x kernels.
+struct XBlock {
+    int y0, z, b;
+};
+__device__ __forceinline__ XBlock x_block(int blk, int nyb, int nz, int ty) {
+    XBlock r;
+    const int yb = blk % nyb;
+    const int zz = blk / nyb;
+    r.y0 = yb * ty;
+    r.z = zz % nz;
+    r.b = zz / nz;
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Forward x kernel, persistent: each workgroup walks row blocks
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the rows of the next block are in
+// flight into registers while the current one is transformed.  Each wavefront
+// transforms its own lines (line j = wave + NW p holds rows 2j, 2j+1; its lanes
+// hold columns n = lane + 64 k) without workgroup barriers; the transposed
+// write of the spectral columns reads across lines.  Partial sums of the source
+// (sum, max |f|) are written per wavefront.
+template <typename T, typename Tin, int NTH, int RMAX>
 __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
-                                              double* __restrict__ partial, XArgs<T> a) {
+                                              double* __restrict__ partial, XArgs<T> a, int nblocks) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
-    __shared__ double red[NTH / 64];
+    constexpr int NW = NTH / 64;
     const int nx = a.nx, ny = a.ny, nz = a.nz, ty = a.ty, ldl = a.ldl;
-    const int y0 = blockIdx.x * ty, z = blockIdx.y, b = blockIdx.z;
-    const int tid = threadIdx.x;
-    const Tin* src = f + ((size_t)b * nz + z) * (size_t)ny * nx;
-
-    // 1. rows -> packed complex lines (row 2j real part, row 2j+1 imaginary part),
-    //    pre-processed for the x transform
-    double acc = 0.0, amax = 0.0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nlines = ty >> 1;
-    const float inv_nx = 1.0f / (float)nx, inv_nl = 1.0f / (float)nlines;
-    for (int i = tid; i < nlines * nx; i += NTH) {
-        const int j = fdiv(i, inv_nx), n = i - j * nx;
-        const int ya = y0 + 2 * j, yb = ya + 1;
-        T va = T(0), vb = T(0);
-        if (ya < ny) {
-            const Tin raw = src[(size_t)ya * nx + n];
-            acc += (double)raw;
-            amax = fmax(amax, fabs((double)raw));
-            va = (T)raw;
-        }
-        if (yb < ny) {
-            const Tin raw = src[(size_t)yb * nx + n];
-            acc += (double)raw;
-            amax = fmax(amax, fabs((double)raw));
-            vb = (T)raw;
-        }
-        int pos = n;
-        if (a.bx != BC_P) {
-            pos = makhoul_pos(n, nx);
-            if (a.bx == BC_D && (n & 1)) {
-                va = -va;
-                vb = -vb;
+    const int nyb = (ny + ty - 1) / ty;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* twl = lds + nlines * ldl;
+    for (int i = tid; i < nx; i += NTH) twl[i] = a.twx[i];
+    const int epl = (nx + 63) >> 6;
+    const float inv_epl = 1.0f / (float)epl, inv_nl = 1.0f / (float)nlines;
+
+    // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
+    Tin ra[RMAX], rb[RMAX];
+    auto fetch = [&](int blk) {
+        const XBlock xb = x_block(blk, nyb, nz, ty);
+        const Tin* src = f + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            const int p = fdiv(r, inv_epl);
+            const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
+            const int ya = xb.y0 + 2 * j;
+            ra[r] = Tin(0);
+            rb[r] = Tin(0);
+            if (j < nlines && n < nx) {
+                if (ya < ny) ra[r] = src[(size_t)ya * nx + n];
+                if (ya + 1 < ny) rb[r] = src[(size_t)(ya + 1) * nx + n];
             }
         }
-        lds[j * ldl + pad(pos)] = mk<T>(va, vb);
-    }
-    const double bsum = block_sum<NTH>(acc, red);
-    const double bmax = block_max<NTH>(amax, red);
-    if (tid == 0) {
-        const size_t blk = ((size_t)b * gridDim.y + z) * gridDim.x + blockIdx.x;
-        partial[2 * blk] = bsum;
-        partial[2 * blk + 1] = bmax;
-    }
-    __syncthreads();
+    };
+    int blk = blockIdx.x;
+    if (blk < nblocks) fetch(blk);
+    __syncthreads();   // twiddles
+    for (; blk < nblocks; blk += gridDim.x) {
+        const XBlock xb = x_block(blk, nyb, nz, ty);
+        // 1. registers -> own packed lines (row 2j real part, row 2j+1 imaginary part),
+        //    pre-processed for the x transform; wavefront sums of the source
+        double acc = 0.0, amax = 0.0;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            const int p = fdiv(r, inv_epl);
+            const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
+            if (j < nlines && n < nx) {
+                acc += (double)ra[r] + (double)rb[r];
+                amax = fmax(amax, fmax(fabs((double)ra[r]), fabs((double)rb[r])));
+                T va = (T)ra[r], vb = (T)rb[r];
+                int pos = n;
+                if (a.bx != BC_P) {
+                    pos = makhoul_pos(n, nx);
+                    if (a.bx == BC_D && (n & 1)) {
+                        va = -va;
+                        vb = -vb;
+                    }
+                }
+                lds[j * ldl + pad(pos)] = mk<T>(va, vb);
+            }
+        }
+        if (blk + (int)gridDim.x < nblocks) fetch(blk + gridDim.x);
+        acc = wave_sum(acc);
+        amax = wave_max(amax);
+        if (lane == 0) {
+            partial[2 * ((size_t)blk * NW + wave)] = acc;
+            partial[2 * ((size_t)blk * NW + wave) + 1] = amax;
+        }
+        // 2. complex FFT of every own line
+        for (int j = wave; j < nlines; j += NW) {
+            wave_lds_sync();
+            wfft<RMAX, false, T>(lds + j * ldl, a.fx, twl, lane);
+        }
+        __syncthreads();
 
-    // 2. complex FFT of every line
-    fft_lines<NTH, kEpt, false, T>(lds, ldl, ty >> 1, a.fx, a.twx);
-
-    // 3. post-process and write columns (y contiguous); one thread per (slot, row pair)
-    cplx<T>* dstS = S + (size_t)b * a.slots * nz * ny;
-    for (int i = tid; i < a.slots * nlines; i += NTH) {
-        const int m = fdiv(i, inv_nl), j = i - m * nlines;
-        const int ya = y0 + 2 * j, yb = ya + 1;
-        const cplx<T>* line = lds + j * ldl;
-        cplx<T> oa, ob;
-        if (a.bx == BC_P) {
-            if (m == 0) {
-                const cplx<T> z0 = line[pad(0)];
-                // X_a[0] = Re Z_0, X_b[0] = Im Z_0; likewise at the Nyquist bin
-                cplx<T> zn = mk<T>(T(0), T(0));
-                if (!(nx & 1)) zn = line[pad(nx >> 1)];
-                oa = mk<T>(z0.x, zn.x);
-                ob = mk<T>(z0.y, zn.y);
+        // 3. post-process and write columns (y contiguous); one thread per (slot, row pair)
+        cplx<T>* dstS = S + (size_t)xb.b * a.slots * nz * ny;
+        for (int i = tid; i < a.slots * nlines; i += NTH) {
+            const int m = fdiv(i, inv_nl), j = i - m * nlines;
+            const int ya = xb.y0 + 2 * j, yb = ya + 1;
+            const cplx<T>* line = lds + j * ldl;
+            cplx<T> oa, ob;
+            if (a.bx == BC_P) {
+                if (m == 0) {
+                    const cplx<T> z0 = line[pad(0)];
+                    // X_a[0] = Re Z_0, X_b[0] = Im Z_0; likewise at the Nyquist bin
+                    cplx<T> zn = mk<T>(T(0), T(0));
+                    if (!(nx & 1)) zn = line[pad(nx >> 1)];
+                    oa = mk<T>(z0.x, zn.x);
+                    ob = mk<T>(z0.y, zn.y);
+                } else {
+                    // X_a[m] = (Z_m + conj Z_{N-m}) / 2,  X_b[m] = (Z_m - conj Z_{N-m}) / (2i)
+                    const cplx<T> zk = line[pad(m)], zr = line[pad(nx - m)];
+                    oa = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                    ob = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+                }
             } else {
-                // X_a[m] = (Z_m + conj Z_{N-m}) / 2,  X_b[m] = (Z_m - conj Z_{N-m}) / (2i)
-                const cplx<T> zk = line[pad(m)], zr = line[pad(nx - m)];
-                oa = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
-                ob = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+                // C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}); real part -> row a, imaginary -> row b
+                const int k0 = 2 * m, k1 = 2 * m + 1;
+                const cplx<T> c0 = dct_bin<T>(line, a.mkx, k0, nx);
+                const cplx<T> c1 = (k1 < nx) ? dct_bin<T>(line, a.mkx, k1, nx) : mk<T>(T(0), T(0));
+                oa = mk<T>(c0.x, c1.x);
+                ob = mk<T>(c0.y, c1.y);
             }
-        } else {
-            // C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}); real part -> row a, imaginary -> row b
-            const int k0 = 2 * m, k1 = 2 * m + 1;
-            const cplx<T> c0 = dct_bin<T>(line, a.mkx, k0, nx);
-            const cplx<T> c1 = (k1 < nx) ? dct_bin<T>(line, a.mkx, k1, nx) : mk<T>(T(0), T(0));
-            oa = mk<T>(c0.x, c1.x);
-            ob = mk<T>(c0.y, c1.y);
+            const size_t col = ((size_t)m * nz + xb.z) * ny;
+            if (ya < ny) dstS[col + ya] = oa;
+            if (yb < ny) dstS[col + yb] = ob;
         }
-        const size_t col = ((size_t)m * nz + z) * ny;
-        if (ya < ny) dstS[col + ya] = oa;
-        if (yb < ny) dstS[col + yb] = ob;
+        __syncthreads();
     }
 }
 
-// Inverse x transform of one z plane slab: spectral columns -> rows.
+// Inverse x transform, persistent like the forward kernel: spectral columns -> rows.
 //   periodic  -> complex-to-real inverse DFT, unnormalised (returns N x);
 //   DCT / DST -> 2 * DCT-III by the inverse of the reordering scheme
 //                (Neumann subsection): W_k = e^{+i pi k/2N} (X_k - i X_{N-k}),
 //                X_N = 0, v = IDFT_unnormalised(W), x_{2m} = v_m,
 //                x_{2m+1} = v_{N-1-m}; Dirichlet multiplies x_n by (-1)^n
 //                (its spectral columns are already stored reversed).
-// MODE XINV_STORE writes u = x - shift[b]; XINV_UPDATE adds to a double u.
-template <typename T, typename Tout, int NTH, int MODE>
+// The gather of the spectral columns reads across lines; the inverse
+// transform and the row writes are per wavefront.
+// MODE XINV_STORE writes u = x - shift[b]; XINV_UPDATE adds to a double u (or,
+// with accumulate = 0, stores the first solution without reading u) and writes
+// per-wavefront partials (sum over the gauge region, max |d|, max |u|).
+template <typename T, typename Tout, int NTH, int MODE, int RMAX>
 __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tout* __restrict__ u, XArgs<T> a,
                                               const double* __restrict__ shift, const double* __restrict__ scalars,
-                                              int gauge_region, double* __restrict__ partial) {
+                                              int gauge_region, double* __restrict__ partial, int nblocks,
+                                              int accumulate) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
-    __shared__ double red[NTH / 64];
+    constexpr int NW = NTH / 64;
+    constexpr int PAIRS = RMAX / 2;    // (slot, row pair) gathers per thread: slots * nlines <= NTH * PAIRS
     const int nx = a.nx, ny = a.ny, nz = a.nz, ty = a.ty, ldl = a.ldl;
-    const int y0 = blockIdx.x * ty, z = blockIdx.y, b = blockIdx.z;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nlines = ty >> 1;
-    const cplx<T>* srcS = S + (size_t)b * a.slots * nz * ny;
-    const float inv_nl = 1.0f / (float)nlines, inv_nx = 1.0f / (float)nx;
+    const int nyb = (ny + ty - 1) / ty;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* twl = lds + nlines * ldl;
+    for (int i = tid; i < nx; i += NTH) twl[i] = a.twx[i];
+    const float inv_nl = 1.0f / (float)nlines;
+    const int npair = a.slots * nlines;
+    const int batch = (int)(nblocks / ((size_t)nyb * nz));
+    const int half = (nx >> 1) + 1;
+    double inv_scale = 1.0;
+    if (MODE == XINV_UPDATE) inv_scale = scalars[SC_INVSCALE];
 
-    // 1. columns -> packed complex spectra of row pairs
-    for (int i = tid; i < a.slots * nlines; i += NTH) {
-        const int m = fdiv(i, inv_nl), j = i - m * nlines;
-        const int ya = y0 + 2 * j, yb = ya + 1;
-        const size_t col = ((size_t)m * nz + z) * ny;
-        const cplx<T> sa = (ya < ny) ? srcS[col + ya] : mk<T>(T(0), T(0));
-        const cplx<T> sb = (yb < ny) ? srcS[col + yb] : mk<T>(T(0), T(0));
-        cplx<T>* line = lds + j * ldl;
-        if (a.bx == BC_P) {
-            if (m == 0) {
-                line[pad(0)] = mk<T>(sa.x, sb.x);
-                if (!(nx & 1)) line[pad(nx >> 1)] = mk<T>(sa.y, sb.y);
-            } else {
-                line[pad(m)] = mk<T>(sa.x - sb.y, sa.y + sb.x);        // X_a + i X_b
-                line[pad(nx - m)] = mk<T>(sa.x + sb.y, sb.x - sa.y);   // conj(X_a) + i conj(X_b)
+    cplx<T> sa[PAIRS], sb[PAIRS];
+    auto fetch = [&](int blk) {
+        const XBlock xb = x_block(blk, nyb, nz, ty);
+        const cplx<T>* srcS = S + (size_t)xb.b * a.slots * nz * ny;
+#pragma unroll
+        for (int k = 0; k < PAIRS; ++k) {
+            const int i = tid + k * NTH;
+            sa[k] = mk<T>(T(0), T(0));
+            sb[k] = sa[k];
+            if (i < npair) {
+                const int m = fdiv(i, inv_nl), j = i - m * nlines;
+                const int ya = xb.y0 + 2 * j;
+                const size_t col = ((size_t)m * nz + xb.z) * ny;
+                if (ya < ny) sa[k] = srcS[col + ya];
+                if (ya + 1 < ny) sb[k] = srcS[col + ya + 1];
             }
-        } else {
-            line[pad(2 * m)] = mk<T>(sa.x, sb.x);
-            if (2 * m + 1 < nx) line[pad(2 * m + 1)] = mk<T>(sa.y, sb.y);
         }
-    }
-    __syncthreads();
-    if (a.bx != BC_P) {
-        const int half = (nx >> 1) + 1;
-        const float inv_half = 1.0f / (float)half;
-        for (int i = tid; i < nlines * half; i += NTH) {
-            const int j = fdiv(i, inv_half), k = i - j * half;
-            if (k == 0) continue;                       // W_0 = X_0
+    };
+    int blk = blockIdx.x;
+    if (blk < nblocks) fetch(blk);
+    for (; blk < nblocks; blk += gridDim.x) {
+        const XBlock xb = x_block(blk, nyb, nz, ty);
+        // 1. registers -> packed complex spectra of row pairs (any line)
+#pragma unroll
+        for (int k = 0; k < PAIRS; ++k) {
+            const int i = tid + k * NTH;
+            if (i < npair) {
+                const int m = fdiv(i, inv_nl), j = i - m * nlines;
+                const cplx<T> va = sa[k], vb = sb[k];
+                cplx<T>* line = lds + j * ldl;
+                if (a.bx == BC_P) {
+                    if (m == 0) {
+                        line[pad(0)] = mk<T>(va.x, vb.x);
+                        if (!(nx & 1)) line[pad(nx >> 1)] = mk<T>(va.y, vb.y);
+                    } else {
+                        line[pad(m)] = mk<T>(va.x - vb.y, va.y + vb.x);        // X_a + i X_b
+                        line[pad(nx - m)] = mk<T>(va.x + vb.y, vb.x - va.y);   // conj(X_a) + i conj(X_b)
+                    }
+                } else {
+                    line[pad(2 * m)] = mk<T>(va.x, vb.x);
+                    if (2 * m + 1 < nx) line[pad(2 * m + 1)] = mk<T>(va.y, vb.y);
+                }
+            }
+        }
+        if (blk + (int)gridDim.x < nblocks) fetch(blk + gridDim.x);
+        __syncthreads();
+
+        const double sh = shift ? shift[xb.b] : 0.0;
+        double gshift = 0.0;
+        if (MODE == XINV_UPDATE) gshift = scalars[SC_COUNT + 2 * batch + xb.b];
+        double acc = 0.0, dmax = 0.0, umax = 0.0;
+        Tout* dst = u + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+        // 2. per own line: inverse pre-processing, inverse FFT, row writes
+        for (int j = wave; j < nlines; j += NW) {
             cplx<T>* line = lds + j * ldl;
-            const cplx<T> xk = line[pad(k)];
-            if (2 * k == nx) {
-                line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), a.mkx[k]);   // e^{+} (X_k - i X_k)
-            } else {
-                const cplx<T> xr = line[pad(nx - k)];
-                // X_k - i X_{N-k} = (xk.x + xr.y, xk.y - xr.x)
-                line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), a.mkx[k]);
-                line[pad(nx - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), a.mkx[nx - k]);
+            if (a.bx != BC_P) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0) continue;                       // W_0 = X_0
+                    const cplx<T> xk = line[pad(k)];
+                    if (2 * k == nx) {
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), a.mkx[k]);   // e^{+} (X_k - i X_k)
+                    } else {
+                        const cplx<T> xr = line[pad(nx - k)];
+                        // X_k - i X_{N-k} = (xk.x + xr.y, xk.y - xr.x)
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), a.mkx[k]);
+                        line[pad(nx - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), a.mkx[nx - k]);
+                    }
+                }
+            }
+            wave_lds_sync();
+            wfft<RMAX, true, T>(line, a.fx, twl, lane);
+            for (int n = lane; n < nx; n += 64) {
+                int pos = n;
+                if (a.bx != BC_P) pos = makhoul_pos(n, nx);
+                cplx<T> c = line[pad(pos)];
+                if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    const int y = xb.y0 + 2 * j + part;
+                    if (y >= ny) continue;
+                    const T v = part ? c.y : c.x;
+                    const size_t idx = (size_t)y * nx + n;
+                    if (MODE == XINV_STORE) {
+                        dst[idx] = (Tout)((double)v - sh);
+                    } else {
+                        const double d = ((double)v - sh) * inv_scale;
+                        const double un = (accumulate ? (double)dst[idx] : 0.0) + d - gshift;
+                        dst[idx] = (Tout)un;
+                        if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
+                        dmax = fmax(dmax, fabs(d));
+                        umax = fmax(umax, fabs(un));
+                    }
+                }
+            }
+        }
+        if (MODE == XINV_UPDATE) {
+            acc = wave_sum(acc);
+            dmax = wave_max(dmax);
+            umax = wave_max(umax);
+            if (lane == 0) {
+                const size_t w = (size_t)blk * NW + wave;
+                partial[3 * w] = acc;
+                partial[3 * w + 1] = dmax;
+                partial[3 * w + 2] = umax;
             }
         }
         __syncthreads();
     }
-
-    // 2. inverse complex FFT (unnormalised)
-    fft_lines<NTH, kEpt, true, T>(lds, ldl, nlines, a.fx, a.twx);
-
-    // 3. rows out
-    const double sh = shift ? shift[b] : 0.0;
-    double inv_scale = 1.0, gshift = 0.0;
-    if (MODE == XINV_UPDATE) {
-        inv_scale = scalars[SC_INVSCALE];
-        gshift = scalars[SC_COUNT + 2 * (int)gridDim.z + b];
-    }
-    double acc = 0.0, dmax = 0.0, umax = 0.0;
-    Tout* dst = u + ((size_t)b * nz + z) * (size_t)ny * nx;
-    for (int i = tid; i < nlines * nx; i += NTH) {
-        const int j = fdiv(i, inv_nx), n = i - j * nx;
-        int pos = n;
-        if (a.bx != BC_P) pos = makhoul_pos(n, nx);
-        cplx<T> c = lds[j * ldl + pad(pos)];
-        if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
-#pragma unroll
-        for (int part = 0; part < 2; ++part) {
-            const int y = y0 + 2 * j + part;
-            if (y >= ny) continue;
-            const T v = part ? c.y : c.x;
-            const size_t idx = (size_t)y * nx + n;
-            if (MODE == XINV_STORE) {
-                dst[idx] = (Tout)((double)v - sh);
-            } else {
-                const double d = ((double)v - sh) * inv_scale;
-                const double un = (double)dst[idx] + d - gshift;
-                dst[idx] = (Tout)un;
-                if (gauge_region == 1 || (gauge_region == 2 && z == 0)) acc += un;
-                dmax = fmax(dmax, fabs(d));
-                umax = fmax(umax, fabs(un));
-            }
-        }
-    }
-    if (MODE == XINV_UPDATE) {
-        const double bs = block_sum<NTH>(acc, red);
-        const double bd = block_max<NTH>(dmax, red);
-        const double bu = block_max<NTH>(umax, red);
-        if (tid == 0) {
-            const size_t blk = ((size_t)b * gridDim.y + z) * gridDim.x + blockIdx.x;
-            partial[3 * blk] = bs;
-            partial[3 * blk + 1] = bd;
-            partial[3 * blk + 2] = bu;
-        }
-    }
 }
 
 template <typename T> static size_t x_lds_bytes(const XArgs<T>& a) {
-    return (size_t)(a.ty >> 1) * a.ldl * sizeof(cplx<T>);
+    return ((size_t)(a.ty >> 1) * a.ldl + a.nx) * sizeof(cplx<T>);
 }
 
-// Allow the kernel the full dynamic LDS budget (beyond the 64 KiB default).
+// Allow the kernel the dynamic LDS it may ask for (lines + twiddles).
 template <typename K> static void allow_lds(K kernel) {
     static bool done = false;
     if (!done) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)((kXElems + kXElems / 8) * sizeof(cplx<double>)));
+                                  kXLdsBytes);
         done = true;
     }
 }
 
+// Persistent grid: a few resident workgroups per CU.
+static int x_grid(int nblocks) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    return nblocks < cus * kXBlocksPerCU ? nblocks : cus * kXBlocksPerCU;
+}
+
+static int x_blocks(int ny, int ty, int nz, int batch) { return ((ny + ty - 1) / ty) * nz * batch; }
+
+template <typename T, typename Tin, int RMAX>
+static hipError_t launch_xfwd_shape(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+                                    hipStream_t s) {
+    const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
+    allow_lds(k_xfwd<T, Tin, kXThreads, RMAX>);
+    hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX>), dim3(x_grid(nb)), dim3(kXThreads), x_lds_bytes(a), s, f,
+                       S, partial, a, nb);
+    return hipGetLastError();
+}
+
 template <typename T, typename Tin>
 hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch, hipStream_t s) {
-    dim3 grid((a.ny + a.ty - 1) / a.ty, a.nz, batch);
-    allow_lds(k_xfwd<T, Tin, kXThreads>);
-    hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads>), grid, dim3(kXThreads), x_lds_bytes(a), s, f, S, partial, a);
+    if (a.nx <= 512) return launch_xfwd_shape<T, Tin, 8>(f, S, partial, a, batch, s);
+    if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, 16>(f, S, partial, a, batch, s);
+    return launch_xfwd_shape<T, Tin, 32>(f, S, partial, a, batch, s);
+}
+
+template <typename T, typename Tout, int MODE, int RMAX>
+static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
+                                    const double* scalars, int gauge_region, double* partial, int accumulate,
+                                    hipStream_t s) {
+    const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
+    allow_lds(k_xinv<T, Tout, kXThreads, MODE, RMAX>);
+    hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, MODE, RMAX>), dim3(x_grid(nb)), dim3(kXThreads), x_lds_bytes(a),
+                       s, S, u, a, shift, scalars, gauge_region, partial, nb, accumulate);
     return hipGetLastError();
+}
+
+template <typename T, typename Tout, int MODE>
+static hipError_t launch_xinv_any(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
+                                  const double* scalars, int gauge_region, double* partial, int accumulate,
+                                  hipStream_t s) {
+    if (a.nx <= 512)
+        return launch_xinv_shape<T, Tout, MODE, 8>(S, u, a, batch, shift, scalars, gauge_region, partial, accumulate,
+                                                   s);
+    if (a.nx <= 1024)
+        return launch_xinv_shape<T, Tout, MODE, 16>(S, u, a, batch, shift, scalars, gauge_region, partial,
+                                                    accumulate, s);
+    return launch_xinv_shape<T, Tout, MODE, 32>(S, u, a, batch, shift, scalars, gauge_region, partial, accumulate, s);
 }
 
 template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift, hipStream_t s) {
-    dim3 grid((a.ny + a.ty - 1) / a.ty, a.nz, batch);
-    allow_lds(k_xinv<T, Tout, kXThreads, XINV_STORE>);
-    hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, XINV_STORE>), grid, dim3(kXThreads), x_lds_bytes(a), s, S, u, a,
-                       shift, (const double*)nullptr, 0, (double*)nullptr);
-    return hipGetLastError();
+    return launch_xinv_any<T, Tout, XINV_STORE>(S, u, a, batch, shift, (const double*)nullptr, 0, (double*)nullptr,
+                                                0, s);
 }
 
 hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float>& a, int batch,
-                              const double* scalars, int gauge_region, double* partial, hipStream_t s) {
-    dim3 grid((a.ny + a.ty - 1) / a.ty, a.nz, batch);
+                              const double* scalars, int gauge_region, double* partial, int accumulate,
+                              hipStream_t s) {
     const double* shift = scalars + SC_COUNT + batch;   // cmean of the correction solve
-    allow_lds(k_xinv<float, double, kXThreads, XINV_UPDATE>);
-    hipLaunchKernelGGL((k_xinv<float, double, kXThreads, XINV_UPDATE>), grid, dim3(kXThreads), x_lds_bytes(a), s, S, u,
-                       a, shift, scalars, gauge_region, partial);
-    return hipGetLastError();
+    return launch_xinv_any<float, double, XINV_UPDATE>(S, u, a, batch, shift, scalars, gauge_region, partial,
+                                                       accumulate, s);
 }
 
 template hipError_t launch_xfwd<double, double>(const double*, cplx<double>*, double*, const XArgs<double>&, int,

@@ -33,42 +33,48 @@
 
 namespace pp {
 
-// Reciprocal pivot of row z for an owned entry: the last row, a tabulated row
-// (z < lmax), or the converged value.
+// Per-lane share of a chunk: a wavefront owns planes wave, wave + NW, ...; its
+// lanes hold elements y = lane + 64 k of each.  Register r of a lane covers
+// plane p = r / epl and element k = r % epl of that plane (epl = ceil(ny/64)).
+struct LaneSlot {
+    int l, y;
+};
+__device__ __forceinline__ LaneSlot lane_slot(int r, int epl, float inv_epl, int wave, int nw, int lane) {
+    const int p = fdiv(r, inv_epl);
+    LaneSlot s;
+    s.l = wave + nw * p;
+    s.y = lane + 64 * (r - p * epl);
+    return s;
+}
+
+// Planes whose pivots and right-hand sides are fetched ahead of each stretch of
+// the (serial) z recurrences.
+constexpr int kZBatch = 4;
+
+// Tabulated reciprocal pivot of plane z for entry e (converged / last-row values come from registers).
 template <typename T>
-__device__ __forceinline__ cplx<T> pivot(const MidArgs<T>& a, int lmax, int roff, int z, int e, cplx<T> winf,
-                                         cplx<T> wlast) {
+__device__ __forceinline__ cplx<T> row_pivot(const MidArgs<T>& a, int lmax, int roff, int z, int e, cplx<T> winf,
+                                             cplx<T> wlast) {
     if (z == a.nz - 1) return wlast;
     if (z < lmax) return a.wrows[(size_t)(roff + z) * a.ny + e];
     return winf;
 }
 
-// Planes whose pivots and right-hand sides are fetched ahead of each stretch of
-// the (serial) forward recurrence.
-constexpr int kZBatch = 4;
-
-// Global -> registers: this thread's entries e = tid + q*NTH (q < OWN) of the
-// nl planes starting at z0, register l*OWN + q.  nl * OWN <= EPT.
-template <typename T, int NTH, int EPT, int OWN>
-__device__ __forceinline__ void fetch_owned(cplx<T> (&r)[EPT], const cplx<T>* __restrict__ col, int z0, int nl,
-                                            int ny) {
-#pragma unroll
-    for (int l = 0; l < EPT / OWN; ++l) {
-#pragma unroll
-        for (int q = 0; q < OWN; ++q) {
-            const int e = threadIdx.x + q * NTH;
-            if (l < nl && e < ny) r[l * OWN + q] = col[(size_t)(z0 + l) * ny + e];
-        }
-    }
-}
-
-template <typename T, int NTH, int EPT, int OWN>
+// The z march.  RMAX: chunk values per lane (64 * RMAX >= ny); OWN: y entries per
+// thread in the z recurrences (NTH * OWN >= ny).
+template <typename T, int NTH, int RMAX, int OWN>
 __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+    constexpr int NW = NTH / 64;
     const int m = blockIdx.x, b = blockIdx.y;
     const int ny = a.ny, nz = a.nz, ldy = a.ldy, zb = a.zb;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // LDS: zb planes of ny (padded), then the y twiddles
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* twl = lds + zb * ldy;
+    for (int i = tid; i < ny; i += NTH) twl[i] = a.twy[i];
     cplx<T>* col = S + ((size_t)b * a.slots + m) * (size_t)nz * ny;
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
@@ -78,9 +84,11 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
     const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
     const int half = (ny >> 1) + 1;
     const int nchunks = (nz + zb - 1) / zb;
-    const float inv_ny = 1.0f / (float)ny, inv_half = 1.0f / (float)half;
+    const int epl = (ny + 63) >> 6;
+    const float inv_epl = 1.0f / (float)epl;
+    const int ppw = (zb + NW - 1) / NW;          // planes per wave per chunk (ppw * epl <= RMAX)
 
-    // owned entries: e = tid + q * NTH; converged and last-row pivots kept in registers
+    // owned z-recurrence entries e = tid + q * NTH; converged and last-row pivots in registers
     cplx<T> st[OWN], winf[OWN], wlast[OWN];
 #pragma unroll
     for (int q = 0; q < OWN; ++q) {
@@ -94,64 +102,69 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
         }
     }
 
-    cplx<T> pre[EPT];
+    cplx<T> pre[RMAX];
+    auto fetch = [&](int z0, int nl) {
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            const LaneSlot ls = lane_slot(r, epl, inv_epl, wave, NW, lane);
+            if (r < ppw * epl && ls.l < nl && ls.y < ny) pre[r] = col[(size_t)(z0 + ls.l) * ny + ls.y];
+        }
+    };
+
     // ------------------------------------------------------------- upward
-    fetch_owned<T, NTH, EPT, OWN>(pre, col, 0, min(zb, nz), ny);
+    fetch(0, min(zb, nz));
     for (int c = 0; c < nchunks; ++c) {
         const int zc = c * zb;
         const int nl = min(zb, nz - zc);
-        // prefetched values -> LDS, pre-processed for the y transform
+        // own planes: prefetched values -> LDS, pre-processed for the y transform
 #pragma unroll
-        for (int l = 0; l < EPT / OWN; ++l) {
-#pragma unroll
-            for (int q = 0; q < OWN; ++q) {
-                const int y = tid + q * NTH;
-                if (l < nl && y < ny) {
-                    cplx<T> v = pre[l * OWN + q];
-                    int pos = y;
-                    if (a.by != BC_P) {
-                        pos = makhoul_pos(y, ny);
-                        if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+        for (int r = 0; r < RMAX; ++r) {
+            const LaneSlot ls = lane_slot(r, epl, inv_epl, wave, NW, lane);
+            if (r < ppw * epl && ls.l < nl && ls.y < ny) {
+                cplx<T> v = pre[r];
+                int pos = ls.y;
+                if (a.by != BC_P) {
+                    pos = makhoul_pos(ls.y, ny);
+                    if (a.by == BC_D && (ls.y & 1)) v = mk<T>(-v.x, -v.y);
+                }
+                lds[ls.l * ldy + pad(pos)] = v;
+            }
+        }
+        if (c + 1 < nchunks) fetch(zc + zb, min(zb, nz - zc - zb));
+        if (c == 0) __syncthreads();   // twiddles
+        // forward y transform of each own plane, then its post-processing
+        for (int l = wave; l < nl; l += NW) {
+            cplx<T>* line = lds + l * ldy;
+            wave_lds_sync();
+            wfft<RMAX, false, T>(line, a.fy, twl, lane);
+            if (a.by != BC_P) {
+                // DCT-II post-twiddle over the pairs (k, ny-k)
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0) continue;
+                    const cplx<T> vk = line[pad(k)];
+                    const cplx<T> wk = a.mky[k];
+                    if (2 * k == ny) {
+                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vk, wk)), T(0.5));
+                    } else {
+                        const cplx<T> vr = line[pad(ny - k)];
+                        const cplx<T> wr = a.mky[ny - k];
+                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), T(0.5));
+                        line[pad(ny - k)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), T(0.5));
                     }
-                    lds[l * ldy + pad(pos)] = v;
+                }
+            } else if (sep) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0 || 2 * k >= ny) continue;
+                    const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
+                    line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                    line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
                 }
             }
         }
-        if (c + 1 < nchunks) fetch_owned<T, NTH, EPT, OWN>(pre, col, zc + zb, min(zb, nz - zc - zb), ny);
         __syncthreads();
-        fft_lines<NTH, EPT, false, T>(lds, ldy, nl, a.fy, a.twy);
-        if (a.by != BC_P) {
-            // DCT-II post-twiddle over the pairs (k, ny-k)
-            for (int i = tid; i < nl * half; i += NTH) {
-                const int l = fdiv(i, inv_half), k = i - l * half;
-                if (k == 0) continue;
-                cplx<T>* line = lds + l * ldy;
-                const cplx<T> vk = line[pad(k)];
-                const cplx<T> wk = a.mky[k];
-                if (2 * k == ny) {
-                    const cplx<T> cc = cadd(cmul(wk, vk), cmulc(vk, wk));
-                    line[pad(k)] = cscale(cc, T(0.5));
-                } else {
-                    const cplx<T> vr = line[pad(ny - k)];
-                    const cplx<T> wr = a.mky[ny - k];
-                    line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), T(0.5));
-                    line[pad(ny - k)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), T(0.5));
-                }
-            }
-            __syncthreads();
-        } else if (sep) {
-            for (int i = tid; i < nl * half; i += NTH) {
-                const int l = fdiv(i, inv_half), k = i - l * half;
-                if (k == 0 || 2 * k >= ny) continue;
-                cplx<T>* line = lds + l * ldy;
-                const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
-                line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
-                line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
-            }
-            __syncthreads();
-        }
-        // forward elimination, kZBatch planes at a time (pivots fetched before the
-        // recurrence); the eliminated right-hand sides go straight back to HBM
+        // forward elimination across the chunk's planes, kZBatch planes at a time
+        // (pivots and right-hand sides fetched ahead of the dependent steps);
+        // eliminated right-hand sides go to HBM
 #pragma unroll
         for (int q = 0; q < OWN; ++q) {
             const int e = tid + q * NTH;
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
                     for (int j = 0; j < kZBatch; ++j) {
                         const int l = l0 + j;
                         if (l < nl) {
-                            w[j] = pivot(a, lmax, roff, zc + l, e, winf[q], wlast[q]);
+                            w[j] = row_pivot(a, lmax, roff, zc + l, e, winf[q], wlast[q]);
                             d[j] = cscale(lds[l * ldy + pad(e)], scale);
                         }
                     }
@@ -185,100 +198,108 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
     }
 
     // ----------------------------------------------------------- downward
-    // Each thread's eliminated values come back in its own prefetch registers,
-    // so back substitution runs on registers and only the result goes to LDS.
 #pragma unroll
     for (int q = 0; q < OWN; ++q) st[q] = mk<T>(T(0), T(0));
     double csum = 0.0;
-    {
-        const int zc = (nchunks - 1) * zb;
-        fetch_owned<T, NTH, EPT, OWN>(pre, col, zc, nz - zc, ny);
-    }
+    fetch((nchunks - 1) * zb, nz - (nchunks - 1) * zb);
     for (int c = nchunks - 1; c >= 0; --c) {
         const int zc = c * zb;
         const int nl = min(zb, nz - zc);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            const LaneSlot ls = lane_slot(r, epl, inv_epl, wave, NW, lane);
+            if (r < ppw * epl && ls.l < nl && ls.y < ny) lds[ls.l * ldy + pad(ls.y)] = pre[r];
+        }
+        if (c > 0) fetch(zc - zb, zb);
+        __syncthreads();
+        // back substitution across the chunk's planes, kZBatch planes at a time
 #pragma unroll
         for (int q = 0; q < OWN; ++q) {
             const int e = tid + q * NTH;
             if (e < ny) {
                 cplx<T> nxt = st[q];
+                for (int l1 = nl - 1; l1 >= 0; l1 -= kZBatch) {
+                    cplx<T> w[kZBatch], dp[kZBatch];
 #pragma unroll
-                for (int l = EPT / OWN - 1; l >= 0; --l) {
-                    if (l < nl) {
-                        const cplx<T> w = pivot(a, lmax, roff, zc + l, e, winf[q], wlast[q]);
-                        const cplx<T> dp = pre[l * OWN + q];
-                        nxt = mk<T>(dp.x - w.x * nxt.x, dp.y - w.y * nxt.y);
-                        lds[l * ldy + pad(e)] = nxt;
-                        if (sing && e == 0) csum += (double)nxt.x;
+                    for (int j = 0; j < kZBatch; ++j) {
+                        const int l = l1 - j;
+                        if (l >= 0) {
+                            w[j] = row_pivot(a, lmax, roff, zc + l, e, winf[q], wlast[q]);
+                            dp[j] = lds[l * ldy + pad(e)];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < kZBatch; ++j) {
+                        const int l = l1 - j;
+                        if (l >= 0) {
+                            nxt = mk<T>(dp[j].x - w[j].x * nxt.x, dp[j].y - w[j].y * nxt.y);
+                            lds[l * ldy + pad(e)] = nxt;
+                            if (sing && e == 0) csum += (double)nxt.x;
+                        }
                     }
                 }
                 st[q] = nxt;
             }
         }
-        if (c > 0) fetch_owned<T, NTH, EPT, OWN>(pre, col, zc - zb, zb, ny);
         __syncthreads();
-        if (a.by != BC_P) {
-            // DCT-III pre-twiddle: W_k = e^{+i pi k/2N} (X_k - i X_{N-k}), X_N = 0
-            for (int i = tid; i < nl * half; i += NTH) {
-                const int l = fdiv(i, inv_half), k = i - l * half;
-                if (k == 0) continue;
-                cplx<T>* line = lds + l * ldy;
-                const cplx<T> xk = line[pad(k)];
-                if (2 * k == ny) {
-                    line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), a.mky[k]);
-                } else {
-                    const cplx<T> xr = line[pad(ny - k)];
-                    line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), a.mky[k]);
-                    line[pad(ny - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), a.mky[ny - k]);
+        // inverse y transform of each own plane, written straight to HBM
+        for (int l = wave; l < nl; l += NW) {
+            cplx<T>* line = lds + l * ldy;
+            if (a.by != BC_P) {
+                // DCT-III pre-twiddle: W_k = e^{+i pi k/2N} (X_k - i X_{N-k}), X_N = 0
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0) continue;
+                    const cplx<T> xk = line[pad(k)];
+                    if (2 * k == ny) {
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), a.mky[k]);
+                    } else {
+                        const cplx<T> xr = line[pad(ny - k)];
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), a.mky[k]);
+                        line[pad(ny - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), a.mky[ny - k]);
+                    }
+                }
+            } else if (sep) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0 || 2 * k >= ny) continue;
+                    const cplx<T> A = line[pad(k)], B = line[pad(ny - k)];
+                    line[pad(k)] = mk<T>(A.x - B.y, A.y + B.x);        // A + i B
+                    line[pad(ny - k)] = mk<T>(A.x + B.y, B.x - A.y);   // conj(A) + i conj(B)
                 }
             }
-            __syncthreads();
-        } else if (sep) {
-            for (int i = tid; i < nl * half; i += NTH) {
-                const int l = fdiv(i, inv_half), k = i - l * half;
-                if (k == 0 || 2 * k >= ny) continue;
-                cplx<T>* line = lds + l * ldy;
-                const cplx<T> A = line[pad(k)], B = line[pad(ny - k)];
-                line[pad(k)] = mk<T>(A.x - B.y, A.y + B.x);        // A + i B
-                line[pad(ny - k)] = mk<T>(A.x + B.y, B.x - A.y);   // conj(A) + i conj(B)
+            wave_lds_sync();
+            wfft<RMAX, true, T>(line, a.fy, twl, lane);
+            for (int y = lane; y < ny; y += 64) {
+                int pos = y;
+                if (a.by != BC_P) pos = makhoul_pos(y, ny);
+                cplx<T> v = line[pad(pos)];
+                if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+                col[(size_t)(zc + l) * ny + y] = v;
             }
-            __syncthreads();
         }
-        fft_lines<NTH, EPT, true, T>(lds, ldy, nl, a.fy, a.twy);
-        for (int i = tid; i < nl * ny; i += NTH) {
-            const int l = fdiv(i, inv_ny), y = i - l * ny;
-            int pos = y;
-            if (a.by != BC_P) pos = makhoul_pos(y, ny);
-            cplx<T> v = lds[l * ldy + pad(pos)];
-            if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
-            col[(size_t)(zc + l) * ny + y] = v;
-        }
-        __syncthreads();
     }
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
 }
 
-template <typename T, int OWN>
-static hipError_t launch_mid_own(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    const size_t lds = (size_t)a.zb * a.ldy * sizeof(cplx<T>);
+template <typename T, int RMAX, int OWN>
+static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+    const size_t lds = zmarch_lds_bytes(a.zb, a.ldy, a.ny, sizeof(cplx<T>));
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zmarch<T, kZThreads, kEpt, OWN>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)((kZElems + kZElems / 8) * sizeof(cplx<double>)));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zmarch<T, kZThreads, RMAX, OWN>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kZLdsBytes);
         attr = true;
     }
-    hipLaunchKernelGGL((k_zmarch<T, kZThreads, kEpt, OWN>), dim3(a.slots, batch), dim3(kZThreads), lds, s, S, a);
+    hipLaunchKernelGGL((k_zmarch<T, kZThreads, RMAX, OWN>), dim3(a.slots, batch), dim3(kZThreads), lds, s, S, a);
     return hipGetLastError();
 }
 
-// Entries per thread: ceil(ny / kZThreads) <= kZOwned.
+// Register shape by line length: ny <= 512 -> 8 values per lane and one z entry
+// per thread; <= 1024 -> 16 and 2; <= 2048 -> 32 and 4.
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    const int own = (a.ny + kZThreads - 1) / kZThreads;
-    if (own <= 1) return launch_mid_own<T, 1>(S, a, batch, s);
-    if (own <= 2) return launch_mid_own<T, 2>(S, a, batch, s);
-    return launch_mid_own<T, kZOwned>(S, a, batch, s);
+    if (a.ny <= 512) return launch_mid_shape<T, 8, 1>(S, a, batch, s);
+    if (a.ny <= 1024) return launch_mid_shape<T, 16, 2>(S, a, batch, s);
+    return launch_mid_shape<T, 32, 4>(S, a, batch, s);
 }
 
 template hipError_t launch_mid<double>(cplx<double>*, const MidArgs<double>&, int, hipStream_t);
