@@ -40,7 +40,7 @@ struct pp_plan_s {
     size_t elem = 0;  // bytes of one complex value of the solve precision
     pp::FftDesc fx{}, fy{};
     int ty = 0, ldl = 0, ldy = 0, zb = 0;
-    size_t nper = 0;  // x-kernel workgroups per batch entry
+    size_t nper = 0;  // upper bound of the x-kernel partial records per batch entry
     // tables (uploaded into the workspace)
     std::vector<unsigned char> blob;
     size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
@@ -373,6 +373,12 @@ pp_status collect(pp_plan p) {
         if ((call) != hipSuccess) return PP_ERR_HIP; \
     } while (0)
 
+// Partial records per batch entry written by the x kernels on this device
+// (<= p->nper, which sizes the partial region of the workspace).
+int x_records(pp_plan p) {
+    return pp::x_grid(pp::x_blocks(p->ny, p->ty, p->nz, p->batch)) * pp::kXWaves;
+}
+
 template <typename T, typename Tio>
 pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStream_t s, bool project, bool demean) {
     pp::XArgs<T> xa = make_xargs<T>(p, ws);
@@ -385,7 +391,7 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
     if ((st = mark(p, s, 0)) != PP_OK) return st;
     PP_HIP((pp::launch_xfwd<T, Tio>(f, S, partial, xa, p->batch, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
-    PP_HIP(pp::launch_finalize_xfwd(partial, (int)p->nper, p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
+    PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
                                     sc + pp::SC_MAXF, s));
     if ((st = mark(p, s, 1)) != PP_OK) return st;
     PP_HIP(pp::launch_mid<T>(S, ma, p->batch, s));
@@ -429,7 +435,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     if ((st = mark(p, s, 0)) != PP_OK) return st;
     PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
-    PP_HIP(pp::launch_finalize_xfwd(partial, (int)p->nper, p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
+    PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
                                     sc + pp::SC_MAXF, s));
     if ((st = mark(p, s, 1)) != PP_OK) return st;
     PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
@@ -437,7 +443,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     if ((st = mark(p, s, 2)) != PP_OK) return st;
     PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 0, s));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
-    PP_HIP(pp::launch_finalize_update(partial, (int)p->nper, p->batch, nregion, sc, 1, s));
+    PP_HIP(pp::launch_finalize_update(partial, x_records(p), p->batch, nregion, sc, 1, s));
     if ((st = mark(p, s, -1)) != PP_OK) return st;
     p->last_iters = 0;
     p->last_rel = 1.0;
@@ -447,13 +453,13 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         if ((st = mark(p, s, 0)) != PP_OK) return st;
         PP_HIP((pp::launch_xfwd<float, float>(r, S, partial, xa, p->batch, s)));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
-        PP_HIP(pp::launch_finalize_xfwd(partial, (int)p->nper, p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
+        PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
         if ((st = mark(p, s, 1)) != PP_OK) return st;
         PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
         if ((st = mark(p, s, 2)) != PP_OK) return st;
         PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 1, s));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
-        PP_HIP(pp::launch_finalize_update(partial, (int)p->nper, p->batch, nregion, sc, 0, s));
+        PP_HIP(pp::launch_finalize_update(partial, x_records(p), p->batch, nregion, sc, 0, s));
         if ((st = mark(p, s, -1)) != PP_OK) return st;
         double h[8];
         PP_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -587,8 +593,9 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         return PP_ERR_SIZE;
     }
     p->ty = 2 * lines;
-    // per-batch partial records: one per wavefront of every x-kernel row block
-    p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz * pp::kXWaves;
+    // partial records per batch entry: one per (workgroup, wavefront) of the persistent
+    // x kernels, whose grid never exceeds the row blocks of all batch entries
+    p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz * batch * pp::kXWaves;
     if (f64) build_tables<double>(p);
     else build_tables<float>(p);
 

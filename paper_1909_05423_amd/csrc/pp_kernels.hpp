@@ -87,6 +87,11 @@ struct ResidualArgs {
 };
 
 // --- launchers (return hipError_t of the launch) -----------------------------
+// Row blocks of the x kernels and the persistent grid they run on; the x kernels
+// write one partial record per (batch entry, workgroup, wavefront).
+int x_blocks(int ny, int ty, int nz, int batch);
+int x_grid(int nblocks);
+
 template <typename T, typename Tin>
 hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch, hipStream_t s);
 

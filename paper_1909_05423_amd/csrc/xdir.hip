@@ -103,14 +103,39 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
             }
         }
     };
+    // per-wavefront sums of the source, one record per (batch entry, workgroup, wavefront)
+    const int batch = (int)(nblocks / ((size_t)nyb * nz));
+    const size_t rec_per_batch = (size_t)gridDim.x * NW;
+    if (lane == 0) {
+        for (int bb = 0; bb < batch; ++bb) {
+            const size_t rec = bb * rec_per_batch + (size_t)blockIdx.x * NW + wave;
+            partial[2 * rec] = 0.0;
+            partial[2 * rec + 1] = 0.0;
+        }
+    }
+    double acc = 0.0, amax = 0.0;
+    int cur_b = -1;
+    auto flush = [&]() {
+        const double s_ = wave_sum(acc), m_ = wave_max(amax);
+        if (lane == 0 && cur_b >= 0) {
+            const size_t rec = cur_b * rec_per_batch + (size_t)blockIdx.x * NW + wave;
+            partial[2 * rec] = s_;
+            partial[2 * rec + 1] = m_;
+        }
+        acc = 0.0;
+        amax = 0.0;
+    };
     int blk = blockIdx.x;
     if (blk < nblocks) fetch(blk);
     __syncthreads();   // twiddles
     for (; blk < nblocks; blk += gridDim.x) {
         const XBlock xb = x_block(blk, nyb, nz, ty);
+        if (xb.b != cur_b) {
+            flush();
+            cur_b = xb.b;
+        }
         // 1. registers -> own packed lines (row 2j real part, row 2j+1 imaginary part),
         //    pre-processed for the x transform; wavefront sums of the source
-        double acc = 0.0, amax = 0.0;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             const int p = fdiv(r, inv_epl);
@@ -131,12 +156,6 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
             }
         }
         if (blk + (int)gridDim.x < nblocks) fetch(blk + gridDim.x);
-        acc = wave_sum(acc);
-        amax = wave_max(amax);
-        if (lane == 0) {
-            partial[2 * ((size_t)blk * NW + wave)] = acc;
-            partial[2 * ((size_t)blk * NW + wave) + 1] = amax;
-        }
         // 2. complex FFT of every own line
         for (int j = wave; j < nlines; j += NW) {
             wave_lds_sync();
@@ -179,6 +198,7 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
         }
         __syncthreads();
     }
+    flush();
 }
 
 // Inverse x transform, persistent like the forward kernel: spectral columns -> rows.
@@ -216,6 +236,32 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     double inv_scale = 1.0;
     if (MODE == XINV_UPDATE) inv_scale = scalars[SC_INVSCALE];
 
+    // refinement partials, one record per (batch entry, workgroup, wavefront)
+    const size_t rec_per_batch = (size_t)gridDim.x * NW;
+    if (MODE == XINV_UPDATE && lane == 0) {
+        for (int bb = 0; bb < batch; ++bb) {
+            const size_t rec = bb * rec_per_batch + (size_t)blockIdx.x * NW + wave;
+            partial[3 * rec] = 0.0;
+            partial[3 * rec + 1] = 0.0;
+            partial[3 * rec + 2] = 0.0;
+        }
+    }
+    double acc = 0.0, dmax = 0.0, umax = 0.0;
+    int cur_b = -1;
+    auto flush = [&]() {
+        if (MODE != XINV_UPDATE) return;
+        const double s_ = wave_sum(acc), d_ = wave_max(dmax), u_ = wave_max(umax);
+        if (lane == 0 && cur_b >= 0) {
+            const size_t rec = cur_b * rec_per_batch + (size_t)blockIdx.x * NW + wave;
+            partial[3 * rec] = s_;
+            partial[3 * rec + 1] = d_;
+            partial[3 * rec + 2] = u_;
+        }
+        acc = 0.0;
+        dmax = 0.0;
+        umax = 0.0;
+    };
+
     cplx<T> sa[PAIRS], sb[PAIRS];
     auto fetch = [&](int blk) {
         const XBlock xb = x_block(blk, nyb, nz, ty);
@@ -238,6 +284,10 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     if (blk < nblocks) fetch(blk);
     for (; blk < nblocks; blk += gridDim.x) {
         const XBlock xb = x_block(blk, nyb, nz, ty);
+        if (xb.b != cur_b) {
+            flush();
+            cur_b = xb.b;
+        }
         // 1. registers -> packed complex spectra of row pairs (any line)
 #pragma unroll
         for (int k = 0; k < PAIRS; ++k) {
@@ -266,7 +316,6 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
         const double sh = shift ? shift[xb.b] : 0.0;
         double gshift = 0.0;
         if (MODE == XINV_UPDATE) gshift = scalars[SC_COUNT + 2 * batch + xb.b];
-        double acc = 0.0, dmax = 0.0, umax = 0.0;
         Tout* dst = u + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
         // 2. per own line: inverse pre-processing, inverse FFT, row writes
         for (int j = wave; j < nlines; j += NW) {
@@ -311,19 +360,9 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                 }
             }
         }
-        if (MODE == XINV_UPDATE) {
-            acc = wave_sum(acc);
-            dmax = wave_max(dmax);
-            umax = wave_max(umax);
-            if (lane == 0) {
-                const size_t w = (size_t)blk * NW + wave;
-                partial[3 * w] = acc;
-                partial[3 * w + 1] = dmax;
-                partial[3 * w + 2] = umax;
-            }
-        }
         __syncthreads();
     }
+    flush();
 }
 
 template <typename T> static size_t x_lds_bytes(const XArgs<T>& a) {
@@ -341,7 +380,7 @@ template <typename K> static void allow_lds(K kernel) {
 }
 
 // Persistent grid: a few resident workgroups per CU.
-static int x_grid(int nblocks) {
+int x_grid(int nblocks) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
@@ -350,7 +389,7 @@ static int x_grid(int nblocks) {
     return nblocks < cus * kXBlocksPerCU ? nblocks : cus * kXBlocksPerCU;
 }
 
-static int x_blocks(int ny, int ty, int nz, int batch) { return ((ny + ty - 1) / ty) * nz * batch; }
+int x_blocks(int ny, int ty, int nz, int batch) { return ((ny + ty - 1) / ty) * nz * batch; }
 
 template <typename T, typename Tin, int RMAX>
 static hipError_t launch_xfwd_shape(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
