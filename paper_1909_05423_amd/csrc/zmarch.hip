@@ -280,6 +280,260 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined z march for ny <= 512: the same stages as k_zmarch, arranged so
+// that the memory traffic of one chunk overlaps the arithmetic of another.
+//
+// A chunk is 8 planes, one per wavefront.  Upward, a lane prefetches its share
+// of its wavefront's plane of the next chunk into registers while the current
+// chunk is transformed and eliminated; the pivots of the next chunk are
+// fetched after the current recurrences.  Downward, a thread prefetches its own
+// entry of the 8 planes of the next chunk (the eliminated right-hand sides),
+// so back substitution runs from registers, and each wavefront then transforms
+// and stores one plane.
+//
+// The order of issue is chosen so that, with in-order completion of vector
+// memory operations, every wait retires only what it needs: at each point of
+// use, the operations issued after the awaited load are a fixed set (one
+// chunk's stores, or one chunk's prefetch).  FULL (ny == 512, nz a multiple of
+// 8) removes every data-dependent branch around memory instructions, so the
+// compiler can count them exactly; barriers order LDS only.
+constexpr int kSZ = 8;        // planes per chunk = wavefronts per workgroup
+constexpr int kSNy = 512;     // longest y line of the pipelined march
+constexpr int kSLdy = 576;    // work-buffer plane stride (>= padded_len(512))
+
+// Workgroup barrier that orders LDS accesses only: the wavefront's LDS
+// operations complete, then all wavefronts meet.  Unlike __syncthreads() it
+// does not wait for outstanding global loads, which the march keeps in flight
+// across barriers.  The memory clobber keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <typename T, bool FULL>
+__global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
+    __shared__ __align__(16) cplx<T> work[kSZ * kSLdy];
+    __shared__ __align__(16) cplx<T> twl[kSNy];
+    __shared__ __align__(16) cplx<T> mkl[kSNy];
+    constexpr int NTH = 512;
+    constexpr int EPL = kSNy / 64;               // plane elements per lane
+    const int m = blockIdx.x, b = blockIdx.y;
+    const int ny = FULL ? kSNy : a.ny;
+    const int nz = a.nz;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int i = tid; i < ny; i += NTH) {
+        twl[i] = a.twy[i];
+        mkl[i] = a.mky[i];
+    }
+    cplx<T>* col = S + ((size_t)b * a.slots + m) * (size_t)nz * ny;
+    const bool pairslot = (a.bx != BC_P) || (m == 0);
+    const bool sep = (a.by == BC_P) && pairslot;
+    const bool sing = a.singular && (m == 0);
+    const int lmax = a.lmax[m], roff = a.rowoff[m];
+    const T scale = a.scale;
+    const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
+    const int half = (ny >> 1) + 1;
+    const int nchunks = (nz + kSZ - 1) / kSZ;
+    const int last = (nchunks - 1) * kSZ;
+
+    // this thread's z-recurrence entry (threads past ny read a valid dummy)
+    const int e = tid;
+    const bool live = FULL || e < ny;
+    const int ec = live ? e : 0;
+    const cplx<T> winf = a.winf[(size_t)m * ny + ec];
+    const cplx<T> wlast = a.wlast[(size_t)m * ny + ec];
+
+    // reciprocal pivots of planes zc .. zc+7 for entry e (planes past the
+    // slot's rows read row 0 of the table, which always exists; the value then
+    // comes from winf / wlast)
+    cplx<T> pv[kSZ];
+    const cplx<T>* wrows = a.wrows + ec;
+    auto load_piv = [&](int zc) {
+#pragma unroll
+        for (int l = 0; l < kSZ; ++l) {
+            const int z = zc + l;
+            pv[l] = wrows[(size_t)((z < lmax) ? roff + z : 0) * ny];
+        }
+    };
+    auto pivot = [&](int z, int l) -> cplx<T> {
+        if (z == nz - 1) return wlast;
+        return (z < lmax) ? pv[l] : winf;
+    };
+    // upward prefetch: elements y = lane + 64 k of plane zc + wave (clamped to the last plane)
+    cplx<T> pre[EPL];
+    auto load_plane = [&](int zc) {
+        const cplx<T>* src = col + (size_t)min(zc + wave, nz - 1) * ny;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int y = lane + 64 * k;
+            pre[k] = src[(FULL || y < ny) ? y : 0];
+        }
+    };
+    // downward prefetch: entry e of planes zc .. zc+7 (clamped to the last plane)
+    auto load_entry = [&](int zc) {
+#pragma unroll
+        for (int l = 0; l < kSZ; ++l) pre[l] = col[(size_t)min(zc + l, nz - 1) * ny + ec];
+    };
+
+    // ------------------------------------------------------------- upward
+    cplx<T> st = mk<T>(T(0), T(0));
+    load_plane(0);
+    load_piv(0);
+    auto up_chunk = [&](int c) {
+        const int zc = c * kSZ;
+        const int nl = FULL ? kSZ : min(kSZ, nz - zc);
+        lds_barrier();   // the previous recurrences are done with the work buffer
+        cplx<T>* line = work + wave * kSLdy;
+        const bool own = FULL || wave < nl;
+        if (own) {
+            // prefetched plane -> work plane, reordered for the forward transform
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) {
+                const int y = lane + 64 * k;
+                if (FULL || y < ny) {
+                    cplx<T> v = pre[k];
+                    int pos = y;
+                    if (a.by != BC_P) {
+                        pos = makhoul_pos(y, ny);
+                        if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+                    }
+                    line[pad(pos)] = v;
+                }
+            }
+        }
+        load_plane(min(zc + kSZ, last));
+        if (own) {
+            wave_lds_sync();
+            wfft<EPL, false, T>(line, a.fy, twl, lane);
+            if (a.by != BC_P) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0) continue;
+                    const cplx<T> vk = line[pad(k)];
+                    const cplx<T> wk = mkl[k];
+                    if (2 * k == ny) {
+                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vk, wk)), T(0.5));
+                    } else {
+                        const cplx<T> vr = line[pad(ny - k)];
+                        const cplx<T> wr = mkl[ny - k];
+                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), T(0.5));
+                        line[pad(ny - k)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), T(0.5));
+                    }
+                }
+            } else if (sep) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0 || 2 * k >= ny) continue;
+                    const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
+                    line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                    line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+                }
+            }
+        }
+        lds_barrier();
+        // forward elimination over the chunk; eliminated right-hand sides go to HBM
+        if (live) {
+            cplx<T> prev = st;
+#pragma unroll
+            for (int l = 0; l < kSZ; ++l) {
+                if (FULL || l < nl) {
+                    const int z = zc + l;
+                    const cplx<T> w = pivot(z, l);
+                    cplx<T> d = cscale(work[l * kSLdy + pad(e)], scale);
+                    if (sing && e == 0) d.x -= proj;
+                    prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
+                    col[(size_t)z * ny + e] = prev;
+                }
+            }
+            st = prev;
+        }
+        load_piv(min(zc + kSZ, last));   // the last chunk reloads its own pivots for the way down
+    };
+    // the first chunk is issued outside the loop so that every pass through the
+    // loop sees the same sequence of memory operations before it
+    up_chunk(0);
+    for (int c = 1; c < nchunks; ++c) up_chunk(c);
+
+    // ----------------------------------------------------------- downward
+    // the top chunk's eliminated right-hand sides were stored by this thread
+    // (same entry, same addresses): read them back in program order
+    load_entry(last);
+    st = mk<T>(T(0), T(0));
+    double csum = 0.0;
+    auto down_chunk = [&](int c) {
+        const int zc = c * kSZ;
+        const int nl = FULL ? kSZ : min(kSZ, nz - zc);
+        lds_barrier();   // the previous inverse transforms are done with the work buffer
+        // back substitution over the chunk, from registers into the work buffer
+        if (live) {
+            cplx<T> nxt = st;
+#pragma unroll
+            for (int j = 0; j < kSZ; ++j) {
+                const int l = kSZ - 1 - j;
+                if (FULL || l < nl) {
+                    const int z = zc + l;
+                    const cplx<T> w = pivot(z, l);
+                    const cplx<T> dp = pre[l];
+                    nxt = mk<T>(dp.x - w.x * nxt.x, dp.y - w.y * nxt.y);
+                    work[l * kSLdy + pad(e)] = nxt;
+                    if (sing && e == 0) csum += (double)nxt.x;
+                }
+            }
+            st = nxt;
+        }
+        lds_barrier();
+        const int zn = zc >= kSZ ? zc - kSZ : 0;
+        load_entry(zn);
+        load_piv(zn);
+        // inverse y transform of this wave's plane, written straight to HBM
+        if (FULL || wave < nl) {
+            cplx<T>* line = work + wave * kSLdy;
+            if (a.by != BC_P) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0) continue;
+                    const cplx<T> xk = line[pad(k)];
+                    if (2 * k == ny) {
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), mkl[k]);
+                    } else {
+                        const cplx<T> xr = line[pad(ny - k)];
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), mkl[k]);
+                        line[pad(ny - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), mkl[ny - k]);
+                    }
+                }
+            } else if (sep) {
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0 || 2 * k >= ny) continue;
+                    const cplx<T> A = line[pad(k)], B = line[pad(ny - k)];
+                    line[pad(k)] = mk<T>(A.x - B.y, A.y + B.x);
+                    line[pad(ny - k)] = mk<T>(A.x + B.y, B.x - A.y);
+                }
+            }
+            wave_lds_sync();
+            wfft<EPL, true, T>(line, a.fy, twl, lane);
+            cplx<T>* dst = col + (size_t)(zc + wave) * ny;
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) {
+                const int y = lane + 64 * k;
+                if (FULL || y < ny) {
+                    int pos = y;
+                    if (a.by != BC_P) pos = makhoul_pos(y, ny);
+                    cplx<T> v = line[pad(pos)];
+                    if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+                    dst[y] = v;
+                }
+            }
+        }
+    };
+    down_chunk(nchunks - 1);
+    for (int c = nchunks - 2; c >= 0; --c) down_chunk(c);
+    if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
+}
+
+template <typename T, bool FULL>
+static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+    hipLaunchKernelGGL((k_zpipe<T, FULL>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
+    return hipGetLastError();
+}
+
 template <typename T, int RMAX, int OWN>
 static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     const size_t lds = zmarch_lds_bytes(a.zb, a.ldy, a.ny, sizeof(cplx<T>));
@@ -293,11 +547,14 @@ static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, h
     return hipGetLastError();
 }
 
-// Register shape by line length: ny <= 512 -> 8 values per lane and one z entry
-// per thread; <= 1024 -> 16 and 2; <= 2048 -> 32 and 4.
+// ny <= 512: the pipelined march; longer lines: k_zmarch with 16 values per lane and
+// two z entries per thread (ny <= 1024) or 32 and 4 (ny <= 2048).
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    if (a.ny <= 512) return launch_mid_shape<T, 8, 1>(S, a, batch, s);
+    if (a.ny <= kSNy) {
+        if (a.ny == kSNy && a.nz % kSZ == 0) return launch_pipe<T, true>(S, a, batch, s);
+        return launch_pipe<T, false>(S, a, batch, s);
+    }
     if (a.ny <= 1024) return launch_mid_shape<T, 16, 2>(S, a, batch, s);
     return launch_mid_shape<T, 32, 4>(S, a, batch, s);
 }
