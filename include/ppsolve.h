@@ -93,8 +93,9 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
 
 /* Refinement controls for PP_F32_REFINED: stop once the estimated relative
  * error of u (max-norm; the size of the next correction predicted from the
- * last two) is at most tol, or after max_iter correction steps (max_iter = 0
- * runs the float solve alone and reports PP_ERR_NOT_CONVERGED). */
+ * last two corrections, or the first correction itself while there is only
+ * one) is at most tol, or after max_iter correction steps (max_iter = 0 runs
+ * the float solve alone and reports PP_ERR_NOT_CONVERGED). */
 pp_status pp_plan_set_refinement(pp_plan p, double tol, int max_iter);
 
 /* Bytes of device workspace the caller must pass to pp_solve/pp_solve_adjoint

@@ -135,11 +135,16 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
     for (int k = z0; k < z1; ++k) {
         const double* p = ub + (size_t)k * plane;
         const double uu = (k + 1 < a.nz) ? p[plane] : z_ghost(uc, ub[0], a.bc[5]);
-        const double lx = ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], -1, uc) +
-                          ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], 1, uc);
-        const double ly = ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], -1, uc) +
-                          ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], 1, uc);
-        const double lap = (lx - 2.0 * uc) * a.ihx2 + (ly - 2.0 * uc) * a.ihy2 + (ud + uu - 2.0 * uc) * a.ihz2;
+        // second differences as sums of first differences: neighbouring values
+        // of a smooth u differ by far less than their size, so each first
+        // difference is exact (Sterbenz) and the stencil's rounding error scales
+        // with |L_h u| rather than with |u| / h^2
+        const double lx = (ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], -1, uc) - uc) +
+                          (ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], 1, uc) - uc);
+        const double ly = (ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], -1, uc) - uc) +
+                          (ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], 1, uc) - uc);
+        const double lz = (ud - uc) + (uu - uc);
+        const double lap = lx * a.ihx2 + ly * a.ihy2 + lz * a.ihz2;
         const size_t idx = base + (size_t)k * plane;
         double fi = f[idx];
         if (a.proj == 1) fi -= mu;

@@ -470,8 +470,10 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         if ((st = collect(p)) != PP_OK) return st;
         if (!std::isfinite(maxf) || !std::isfinite(rel)) return PP_ERR_NONFINITE;
         // estimated error after this correction: the next correction, predicted
-        // from the contraction of the last two
-        const double rho = relprev > 0.0 ? std::min(1.0, rel / relprev) : 1.0;
+        // from the contraction of the last two corrections.  The first correction
+        // has no predecessor (the ratio to the first solution says nothing about
+        // how fast corrections of a residual contract), so it must itself be small.
+        const double rho = (it >= 2 && relprev > 0.0) ? std::min(1.0, rel / relprev) : 1.0;
         if (rel == 0.0 || rel * rho <= p->ir_tol) return PP_OK;
     }
     return PP_ERR_NOT_CONVERGED;
@@ -575,8 +577,11 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         lines = std::min(pp::kXWaves * lpw, (ny + 1) / 2);
         // the inverse gathers slots * lines (slot, row pair) values, rmax/2 per thread
         while (lines > 1 && (size_t)((nx + 1) / 2) * lines > (size_t)pp::kXThreads * (pp::xdir_rmax(nx) / 2)) --lines;
-        const size_t xlds = ((size_t)lines * pp::padded_len(nx) + nx) * p->elem;
-        if (xlds > (size_t)pp::kXLdsBytes) lines = 0;
+        // LDS: the lines plus two twiddle tables of nx; fewer lines to keep two
+        // workgroups per CU, and a single line may use the whole LDS
+        auto xlds = [&](int l) { return ((size_t)l * pp::padded_len(nx) + 2 * (size_t)nx) * p->elem; };
+        while (lines > 1 && xlds(lines) > (size_t)pp::kXLdsBytes) --lines;
+        if (xlds(lines) > (size_t)pp::kXLdsMax) lines = 0;
     }
     // z planes per chunk: each wavefront of the z march transforms whole planes,
     // ppw = rmax / ceil(ny/64) of them per chunk; the LDS holds the chunk and the twiddles

@@ -281,6 +281,13 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier that orders LDS accesses only: the wavefront's LDS
+// operations complete, then all wavefronts meet.  Unlike __syncthreads() it
+// does not wait for outstanding global loads, which the pipelined kernels keep
+// in flight across barriers.  The memory clobber keeps the compiler from moving
+// memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Wavefront-private Stockham stage: the 64 lanes of one wave transform one
 // line in place (all of the wave's reads precede its writes in program order).
 // MAXB = butterflies per lane = ceil(N / R / 64).

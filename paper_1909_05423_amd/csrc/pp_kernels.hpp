@@ -20,7 +20,8 @@ constexpr int kXThreads = 256;                 // x kernels: lines of nx per wor
 constexpr int kXElems = kXThreads * kEpt;
 constexpr int kXBlocksPerCU = 2;               // persistent x-kernel workgroups per CU (all resident)
 constexpr int kXWaves = kXThreads / 64;
-constexpr int kXLdsBytes = 96 * 1024;          // x-kernel LDS ceiling (lines + twiddles)
+constexpr int kXLdsBytes = 96 * 1024;          // x-kernel LDS target (lines + twiddle tables), two workgroups per CU
+constexpr int kXLdsMax = 160 * 1024 - 1024;    // x-kernel LDS ceiling (one workgroup per CU)
 // x-kernel register shape: values per lane of one line (64 * RMAX >= nx).
 constexpr int xdir_rmax(int nx) { return nx <= 512 ? 8 : (nx <= 1024 ? 16 : 32); }
 constexpr int kZThreads = 512;                 // z march: planes per chunk = kZElems / ny
@@ -50,7 +51,9 @@ template <typename T> struct XArgs {
 };
 
 // Solution mode of the inverse x kernel.
-enum XinvMode : int { XINV_STORE = 0, XINV_UPDATE = 1 };
+// XINV_UPDATE adds the correction to u; XINV_FIRST stores the first solution
+// of the refinement without reading u.
+enum XinvMode : int { XINV_STORE = 0, XINV_UPDATE = 1, XINV_FIRST = 2 };
 
 // z-march kernel: one workgroup per (spectral x column, batch entry).
 template <typename T> struct MidArgs {

@@ -30,7 +30,7 @@ namespace pp {
 // One DCT-II bin of a packed pair of rows, from the DFT V of the reordered
 // complex line: C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}), V_N = V_0.
 template <typename T>
-__device__ __forceinline__ cplx<T> dct_bin(const cplx<T>* line, const cplx<T>* __restrict__ mkt, int k, int N) {
+__device__ __forceinline__ cplx<T> dct_bin(const cplx<T>* line, const cplx<T>* mkt, int k, int N) {
     const cplx<T> vk = line[pad(k)];
     const cplx<T> vr = line[pad(k == 0 ? 0 : N - k)];
     const cplx<T> w = mkt[k];
@@ -69,20 +69,33 @@ __device__ __forceinline__ double wave_max(double v) {
 // hold columns n = lane + 64 k) without workgroup barriers; the transposed
 // write of the spectral columns reads across lines.  Partial sums of the source
 // (sum, max |f|) are written per wavefront.
-template <typename T, typename Tin, int NTH, int RMAX>
+//
+// Order of issue per block: lines from the prefetched rows, prefetch of the
+// next block, transforms, column stores.  The wait for a prefetch then only
+// has the previous block's stores behind it.  FULL (nx = 64 RMAX, one line per
+// wavefront, ny a multiple of the block height) has no data-dependent branch
+// around a memory instruction, so that count is exact; the first block is
+// issued outside the loop so every pass through it sees the same sequence.
+template <typename T, typename Tin, int NTH, int RMAX, bool FULL>
 __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
                                               double* __restrict__ partial, XArgs<T> a, int nblocks) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NW = NTH / 64;
-    const int nx = a.nx, ny = a.ny, nz = a.nz, ty = a.ty, ldl = a.ldl;
+    constexpr int PAIRS = RMAX / 2;   // FULL: column writes per thread, slots * nlines == NTH * PAIRS
+    const int nx = FULL ? 64 * RMAX : a.nx;
+    const int ny = a.ny, nz = a.nz, ty = FULL ? 2 * NW : a.ty, ldl = a.ldl;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nlines = ty >> 1;
     const int nyb = (ny + ty - 1) / ty;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* twl = lds + nlines * ldl;
-    for (int i = tid; i < nx; i += NTH) twl[i] = a.twx[i];
-    const int epl = (nx + 63) >> 6;
+    cplx<T>* mkl = twl + nx;
+    for (int i = tid; i < nx; i += NTH) {
+        twl[i] = a.twx[i];
+        mkl[i] = a.mkx[i];
+    }
+    const int epl = FULL ? RMAX : (nx + 63) >> 6;
     const float inv_epl = 1.0f / (float)epl, inv_nl = 1.0f / (float)nlines;
 
     // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
@@ -92,14 +105,19 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
         const Tin* src = f + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            const int p = fdiv(r, inv_epl);
+            const int p = FULL ? 0 : fdiv(r, inv_epl);
             const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
             const int ya = xb.y0 + 2 * j;
-            ra[r] = Tin(0);
-            rb[r] = Tin(0);
-            if (j < nlines && n < nx) {
-                if (ya < ny) ra[r] = src[(size_t)ya * nx + n];
-                if (ya + 1 < ny) rb[r] = src[(size_t)(ya + 1) * nx + n];
+            if (FULL) {
+                ra[r] = src[(size_t)ya * nx + n];
+                rb[r] = src[(size_t)(ya + 1) * nx + n];
+            } else {
+                ra[r] = Tin(0);
+                rb[r] = Tin(0);
+                if (j < nlines && n < nx) {
+                    if (ya < ny) ra[r] = src[(size_t)ya * nx + n];
+                    if (ya + 1 < ny) rb[r] = src[(size_t)(ya + 1) * nx + n];
+                }
             }
         }
     };
@@ -125,22 +143,47 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
         acc = 0.0;
         amax = 0.0;
     };
-    int blk = blockIdx.x;
-    if (blk < nblocks) fetch(blk);
-    __syncthreads();   // twiddles
-    for (; blk < nblocks; blk += gridDim.x) {
+    // post-processed spectral pair (rows ya, ya+1) of slot m from line j
+    auto column = [&](int m, int j, cplx<T>& oa, cplx<T>& ob) {
+        const cplx<T>* line = lds + j * ldl;
+        if (a.bx == BC_P) {
+            if (m == 0) {
+                const cplx<T> z0 = line[pad(0)];
+                // X_a[0] = Re Z_0, X_b[0] = Im Z_0; likewise at the Nyquist bin
+                cplx<T> zn = mk<T>(T(0), T(0));
+                if (!(nx & 1)) zn = line[pad(nx >> 1)];
+                oa = mk<T>(z0.x, zn.x);
+                ob = mk<T>(z0.y, zn.y);
+            } else {
+                // X_a[m] = (Z_m + conj Z_{N-m}) / 2,  X_b[m] = (Z_m - conj Z_{N-m}) / (2i)
+                const cplx<T> zk = line[pad(m)], zr = line[pad(nx - m)];
+                oa = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                ob = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+            }
+        } else {
+            // C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}); real part -> row a, imaginary -> row b
+            const int k0 = 2 * m, k1 = 2 * m + 1;
+            const cplx<T> c0 = dct_bin<T>(line, mkl, k0, nx);
+            const cplx<T> c1 = (FULL || k1 < nx) ? dct_bin<T>(line, mkl, k1, nx) : mk<T>(T(0), T(0));
+            oa = mk<T>(c0.x, c1.x);
+            ob = mk<T>(c0.y, c1.y);
+        }
+    };
+
+    auto step = [&](int blk) {
         const XBlock xb = x_block(blk, nyb, nz, ty);
         if (xb.b != cur_b) {
             flush();
             cur_b = xb.b;
         }
+        lds_barrier();   // the previous column writes are done reading the lines (and the twiddles are in)
         // 1. registers -> own packed lines (row 2j real part, row 2j+1 imaginary part),
         //    pre-processed for the x transform; wavefront sums of the source
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            const int p = fdiv(r, inv_epl);
+            const int p = FULL ? 0 : fdiv(r, inv_epl);
             const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
-            if (j < nlines && n < nx) {
+            if (FULL || (j < nlines && n < nx)) {
                 acc += (double)ra[r] + (double)rb[r];
                 amax = fmax(amax, fmax(fabs((double)ra[r]), fabs((double)rb[r])));
                 T va = (T)ra[r], vb = (T)rb[r];
@@ -155,49 +198,51 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                 lds[j * ldl + pad(pos)] = mk<T>(va, vb);
             }
         }
-        if (blk + (int)gridDim.x < nblocks) fetch(blk + gridDim.x);
-        // 2. complex FFT of every own line
-        for (int j = wave; j < nlines; j += NW) {
+        // the next block's rows (past the end: this block's again, unused)
+        const int nxt = blk + (int)gridDim.x;
+        fetch(nxt < nblocks ? nxt : blk);
+        // 2. complex FFT of every own line (FULL: exactly one)
+        if (FULL) {
             wave_lds_sync();
-            wfft<RMAX, false, T>(lds + j * ldl, a.fx, twl, lane);
+            wfft<RMAX, false, T>(lds + wave * ldl, a.fx, twl, lane);
+        } else {
+            for (int j = wave; j < nlines; j += NW) {
+                wave_lds_sync();
+                wfft<RMAX, false, T>(lds + j * ldl, a.fx, twl, lane);
+            }
         }
-        __syncthreads();
+        lds_barrier();
 
         // 3. post-process and write columns (y contiguous); one thread per (slot, row pair)
         cplx<T>* dstS = S + (size_t)xb.b * a.slots * nz * ny;
-        for (int i = tid; i < a.slots * nlines; i += NTH) {
-            const int m = fdiv(i, inv_nl), j = i - m * nlines;
-            const int ya = xb.y0 + 2 * j, yb = ya + 1;
-            const cplx<T>* line = lds + j * ldl;
-            cplx<T> oa, ob;
-            if (a.bx == BC_P) {
-                if (m == 0) {
-                    const cplx<T> z0 = line[pad(0)];
-                    // X_a[0] = Re Z_0, X_b[0] = Im Z_0; likewise at the Nyquist bin
-                    cplx<T> zn = mk<T>(T(0), T(0));
-                    if (!(nx & 1)) zn = line[pad(nx >> 1)];
-                    oa = mk<T>(z0.x, zn.x);
-                    ob = mk<T>(z0.y, zn.y);
-                } else {
-                    // X_a[m] = (Z_m + conj Z_{N-m}) / 2,  X_b[m] = (Z_m - conj Z_{N-m}) / (2i)
-                    const cplx<T> zk = line[pad(m)], zr = line[pad(nx - m)];
-                    oa = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
-                    ob = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
-                }
-            } else {
-                // C_k = 1/2 (e^{-i pi k/2N} V_k + e^{+i pi k/2N} V_{N-k}); real part -> row a, imaginary -> row b
-                const int k0 = 2 * m, k1 = 2 * m + 1;
-                const cplx<T> c0 = dct_bin<T>(line, a.mkx, k0, nx);
-                const cplx<T> c1 = (k1 < nx) ? dct_bin<T>(line, a.mkx, k1, nx) : mk<T>(T(0), T(0));
-                oa = mk<T>(c0.x, c1.x);
-                ob = mk<T>(c0.y, c1.y);
+        if (FULL) {
+#pragma unroll
+            for (int q = 0; q < PAIRS; ++q) {
+                const int i = tid + q * NTH;
+                const int m = fdiv(i, inv_nl), j = i - m * nlines;
+                const int ya = xb.y0 + 2 * j;
+                cplx<T> oa, ob;
+                column(m, j, oa, ob);
+                const size_t col = ((size_t)m * nz + xb.z) * ny;
+                dstS[col + ya] = oa;
+                dstS[col + ya + 1] = ob;
             }
-            const size_t col = ((size_t)m * nz + xb.z) * ny;
-            if (ya < ny) dstS[col + ya] = oa;
-            if (yb < ny) dstS[col + yb] = ob;
+        } else {
+            for (int i = tid; i < a.slots * nlines; i += NTH) {
+                const int m = fdiv(i, inv_nl), j = i - m * nlines;
+                const int ya = xb.y0 + 2 * j, yb = ya + 1;
+                cplx<T> oa, ob;
+                column(m, j, oa, ob);
+                const size_t col = ((size_t)m * nz + xb.z) * ny;
+                if (ya < ny) dstS[col + ya] = oa;
+                if (yb < ny) dstS[col + yb] = ob;
+            }
         }
-        __syncthreads();
-    }
+    };
+    // the grid never exceeds the number of blocks
+    fetch(blockIdx.x);
+    step(blockIdx.x);
+    for (int blk = blockIdx.x + gridDim.x; blk < nblocks; blk += gridDim.x) step(blk);
     flush();
 }
 
@@ -210,35 +255,40 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
 //                (its spectral columns are already stored reversed).
 // The gather of the spectral columns reads across lines; the inverse
 // transform and the row writes are per wavefront.
-// MODE XINV_STORE writes u = x - shift[b]; XINV_UPDATE adds to a double u (or,
-// with accumulate = 0, stores the first solution without reading u) and writes
-// per-wavefront partials (sum over the gauge region, max |d|, max |u|).
-template <typename T, typename Tout, int NTH, int MODE, int RMAX>
+// MODE XINV_STORE writes u = x - shift[b]; XINV_UPDATE adds the scaled
+// correction to a double u and XINV_FIRST stores it without reading u; both
+// write per-wavefront partials (sum over the gauge region, max |d|, max |u|).
+template <typename T, typename Tout, int NTH, int MODE, int RMAX, bool FULL>
 __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tout* __restrict__ u, XArgs<T> a,
                                               const double* __restrict__ shift, const double* __restrict__ scalars,
-                                              int gauge_region, double* __restrict__ partial, int nblocks,
-                                              int accumulate) {
+                                              int gauge_region, double* __restrict__ partial, int nblocks) {
+    constexpr bool UPD = (MODE != XINV_STORE);   // refinement update (partials, double output)
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NW = NTH / 64;
     constexpr int PAIRS = RMAX / 2;    // (slot, row pair) gathers per thread: slots * nlines <= NTH * PAIRS
-    const int nx = a.nx, ny = a.ny, nz = a.nz, ty = a.ty, ldl = a.ldl;
+    const int nx = FULL ? 64 * RMAX : a.nx;
+    const int ny = a.ny, nz = a.nz, ty = FULL ? 2 * NW : a.ty, ldl = a.ldl;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nlines = ty >> 1;
     const int nyb = (ny + ty - 1) / ty;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* twl = lds + nlines * ldl;
-    for (int i = tid; i < nx; i += NTH) twl[i] = a.twx[i];
+    cplx<T>* mkl = twl + nx;
+    for (int i = tid; i < nx; i += NTH) {
+        twl[i] = a.twx[i];
+        mkl[i] = a.mkx[i];
+    }
     const float inv_nl = 1.0f / (float)nlines;
     const int npair = a.slots * nlines;
     const int batch = (int)(nblocks / ((size_t)nyb * nz));
     const int half = (nx >> 1) + 1;
     double inv_scale = 1.0;
-    if (MODE == XINV_UPDATE) inv_scale = scalars[SC_INVSCALE];
+    if (UPD) inv_scale = scalars[SC_INVSCALE];
 
     // refinement partials, one record per (batch entry, workgroup, wavefront)
     const size_t rec_per_batch = (size_t)gridDim.x * NW;
-    if (MODE == XINV_UPDATE && lane == 0) {
+    if (UPD && lane == 0) {
         for (int bb = 0; bb < batch; ++bb) {
             const size_t rec = bb * rec_per_batch + (size_t)blockIdx.x * NW + wave;
             partial[3 * rec] = 0.0;
@@ -249,7 +299,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     double acc = 0.0, dmax = 0.0, umax = 0.0;
     int cur_b = -1;
     auto flush = [&]() {
-        if (MODE != XINV_UPDATE) return;
+        if (!UPD) return;
         const double s_ = wave_sum(acc), d_ = wave_max(dmax), u_ = wave_max(umax);
         if (lane == 0 && cur_b >= 0) {
             const size_t rec = cur_b * rec_per_batch + (size_t)blockIdx.x * NW + wave;
@@ -269,30 +319,44 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
 #pragma unroll
         for (int k = 0; k < PAIRS; ++k) {
             const int i = tid + k * NTH;
-            sa[k] = mk<T>(T(0), T(0));
-            sb[k] = sa[k];
-            if (i < npair) {
+            if (FULL) {
                 const int m = fdiv(i, inv_nl), j = i - m * nlines;
                 const int ya = xb.y0 + 2 * j;
                 const size_t col = ((size_t)m * nz + xb.z) * ny;
-                if (ya < ny) sa[k] = srcS[col + ya];
-                if (ya + 1 < ny) sb[k] = srcS[col + ya + 1];
+                sa[k] = srcS[col + ya];
+                sb[k] = srcS[col + ya + 1];
+            } else {
+                sa[k] = mk<T>(T(0), T(0));
+                sb[k] = sa[k];
+                if (i < npair) {
+                    const int m = fdiv(i, inv_nl), j = i - m * nlines;
+                    const int ya = xb.y0 + 2 * j;
+                    const size_t col = ((size_t)m * nz + xb.z) * ny;
+                    if (ya < ny) sa[k] = srcS[col + ya];
+                    if (ya + 1 < ny) sb[k] = srcS[col + ya + 1];
+                }
             }
         }
     };
-    int blk = blockIdx.x;
-    if (blk < nblocks) fetch(blk);
-    for (; blk < nblocks; blk += gridDim.x) {
+    // FULL refinement update: the current rows of u for this wave's line, read
+    // before the next block's prefetch is issued
+    constexpr int UR = (MODE == XINV_UPDATE && FULL) ? 2 * RMAX : 1;
+    double uo[UR];
+    for (int r = 0; r < UR; ++r) uo[r] = 0.0;
+
+    auto step = [&](int blk) {
         const XBlock xb = x_block(blk, nyb, nz, ty);
         if (xb.b != cur_b) {
             flush();
             cur_b = xb.b;
         }
+        Tout* dst = u + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+        lds_barrier();   // the previous inverse transforms are done with the lines (and the twiddles are in)
         // 1. registers -> packed complex spectra of row pairs (any line)
 #pragma unroll
         for (int k = 0; k < PAIRS; ++k) {
             const int i = tid + k * NTH;
-            if (i < npair) {
+            if (FULL || i < npair) {
                 const int m = fdiv(i, inv_nl), j = i - m * nlines;
                 const cplx<T> va = sa[k], vb = sb[k];
                 cplx<T>* line = lds + j * ldl;
@@ -306,75 +370,114 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                     }
                 } else {
                     line[pad(2 * m)] = mk<T>(va.x, vb.x);
-                    if (2 * m + 1 < nx) line[pad(2 * m + 1)] = mk<T>(va.y, vb.y);
+                    if (FULL || 2 * m + 1 < nx) line[pad(2 * m + 1)] = mk<T>(va.y, vb.y);
                 }
             }
         }
-        if (blk + (int)gridDim.x < nblocks) fetch(blk + gridDim.x);
-        __syncthreads();
+        if (MODE == XINV_UPDATE && FULL) {
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k)
+#pragma unroll
+                for (int part = 0; part < 2; ++part)
+                    uo[2 * k + part] = (double)dst[(size_t)(xb.y0 + 2 * wave + part) * nx + lane + 64 * k];
+        }
+        // the next block's spectra (past the end: this block's again, unused)
+        const int nxt = blk + (int)gridDim.x;
+        fetch(nxt < nblocks ? nxt : blk);
+        lds_barrier();
 
         const double sh = shift ? shift[xb.b] : 0.0;
         double gshift = 0.0;
-        if (MODE == XINV_UPDATE) gshift = scalars[SC_COUNT + 2 * batch + xb.b];
-        Tout* dst = u + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
-        // 2. per own line: inverse pre-processing, inverse FFT, row writes
-        for (int j = wave; j < nlines; j += NW) {
+        if (UPD) gshift = scalars[SC_COUNT + 2 * batch + xb.b];
+        // 2. per own line (FULL: exactly one): inverse pre-processing, inverse FFT, row writes
+        for (int j = wave; FULL ? j == wave : j < nlines; j += NW) {
             cplx<T>* line = lds + j * ldl;
             if (a.bx != BC_P) {
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0) continue;                       // W_0 = X_0
                     const cplx<T> xk = line[pad(k)];
                     if (2 * k == nx) {
-                        line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), a.mkx[k]);   // e^{+} (X_k - i X_k)
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), mkl[k]);   // e^{+} (X_k - i X_k)
                     } else {
                         const cplx<T> xr = line[pad(nx - k)];
                         // X_k - i X_{N-k} = (xk.x + xr.y, xk.y - xr.x)
-                        line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), a.mkx[k]);
-                        line[pad(nx - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), a.mkx[nx - k]);
+                        line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), mkl[k]);
+                        line[pad(nx - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), mkl[nx - k]);
                     }
                 }
             }
             wave_lds_sync();
             wfft<RMAX, true, T>(line, a.fx, twl, lane);
-            for (int n = lane; n < nx; n += 64) {
-                int pos = n;
-                if (a.bx != BC_P) pos = makhoul_pos(n, nx);
-                cplx<T> c = line[pad(pos)];
-                if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
+            if (FULL) {
 #pragma unroll
-                for (int part = 0; part < 2; ++part) {
-                    const int y = xb.y0 + 2 * j + part;
-                    if (y >= ny) continue;
-                    const T v = part ? c.y : c.x;
-                    const size_t idx = (size_t)y * nx + n;
-                    if (MODE == XINV_STORE) {
-                        dst[idx] = (Tout)((double)v - sh);
-                    } else {
-                        const double d = ((double)v - sh) * inv_scale;
-                        const double un = (accumulate ? (double)dst[idx] : 0.0) + d - gshift;
-                        dst[idx] = (Tout)un;
-                        if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
-                        dmax = fmax(dmax, fabs(d));
-                        umax = fmax(umax, fabs(un));
+                for (int k = 0; k < RMAX; ++k) {
+                    const int n = lane + 64 * k;
+                    int pos = n;
+                    if (a.bx != BC_P) pos = makhoul_pos(n, nx);
+                    cplx<T> c = line[pad(pos)];
+                    if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        const int y = xb.y0 + 2 * j + part;
+                        const T v = part ? c.y : c.x;
+                        const size_t idx = (size_t)y * nx + n;
+                        if (MODE == XINV_STORE) {
+                            dst[idx] = (Tout)((double)v - sh);
+                        } else {
+                            const double d = ((double)v - sh) * inv_scale;
+                            const double un = uo[UR > 1 ? 2 * k + part : 0] + d - gshift;   // uo = 0 for XINV_FIRST
+                            dst[idx] = (Tout)un;
+                            if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
+                            dmax = fmax(dmax, fabs(d));
+                            umax = fmax(umax, fabs(un));
+                        }
+                    }
+                }
+            } else {
+                for (int n = lane; n < nx; n += 64) {
+                    int pos = n;
+                    if (a.bx != BC_P) pos = makhoul_pos(n, nx);
+                    cplx<T> c = line[pad(pos)];
+                    if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        const int y = xb.y0 + 2 * j + part;
+                        if (y >= ny) continue;
+                        const T v = part ? c.y : c.x;
+                        const size_t idx = (size_t)y * nx + n;
+                        if (MODE == XINV_STORE) {
+                            dst[idx] = (Tout)((double)v - sh);
+                        } else {
+                            const double d = ((double)v - sh) * inv_scale;
+                            const double un = (MODE == XINV_UPDATE ? (double)dst[idx] : 0.0) + d - gshift;
+                            dst[idx] = (Tout)un;
+                            if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
+                            dmax = fmax(dmax, fabs(d));
+                            umax = fmax(umax, fabs(un));
+                        }
                     }
                 }
             }
         }
-        __syncthreads();
-    }
+    };
+    // the grid never exceeds the number of blocks
+    fetch(blockIdx.x);
+    step(blockIdx.x);
+    for (int blk = blockIdx.x + gridDim.x; blk < nblocks; blk += gridDim.x) step(blk);
     flush();
 }
 
 template <typename T> static size_t x_lds_bytes(const XArgs<T>& a) {
-    return ((size_t)(a.ty >> 1) * a.ldl + a.nx) * sizeof(cplx<T>);
+    return ((size_t)(a.ty >> 1) * a.ldl + 2 * (size_t)a.nx) * sizeof(cplx<T>);
 }
 
-// Allow the kernel the dynamic LDS it may ask for (lines + twiddles).
-template <typename K> static void allow_lds(K kernel) {
+// Allow the kernel the dynamic LDS it may ask for (lines + twiddle tables);
+// once per kernel (the template argument is the kernel itself).
+template <auto K> static void allow_lds() {
     static bool done = false;
     if (!done) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kXLdsBytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kXLdsMax);
         done = true;
     }
 }
@@ -391,13 +494,29 @@ int x_grid(int nblocks) {
 
 int x_blocks(int ny, int ty, int nz, int batch) { return ((ny + ty - 1) / ty) * nz * batch; }
 
+// Row blocks of the FULL shape: nx = 64 RMAX, one line per wavefront, whole blocks
+// in y.  Lines of 2048 never fit four to a workgroup, so RMAX = 32 has no FULL form.
+template <int RMAX, typename T> static bool x_full(const XArgs<T>& a) {
+    return RMAX <= 16 && a.nx == 64 * RMAX && a.ty == 2 * kXWaves && a.ny % a.ty == 0;
+}
+
 template <typename T, typename Tin, int RMAX>
 static hipError_t launch_xfwd_shape(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
                                     hipStream_t s) {
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
-    allow_lds(k_xfwd<T, Tin, kXThreads, RMAX>);
-    hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX>), dim3(x_grid(nb)), dim3(kXThreads), x_lds_bytes(a), s, f,
-                       S, partial, a, nb);
+    if constexpr (RMAX <= 16) {
+        if (x_full<RMAX>(a)) {
+            allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, true>>();
+            hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, true>), dim3(x_grid(nb)), dim3(kXThreads),
+                               x_lds_bytes(a), s, f, S, partial, a, nb);
+            return hipGetLastError();
+        }
+    }
+    {
+        allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, false>>();
+        hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, false>), dim3(x_grid(nb)), dim3(kXThreads),
+                           x_lds_bytes(a), s, f, S, partial, a, nb);
+    }
     return hipGetLastError();
 }
 
@@ -410,40 +529,47 @@ hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>
 
 template <typename T, typename Tout, int MODE, int RMAX>
 static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
-                                    const double* scalars, int gauge_region, double* partial, int accumulate,
-                                    hipStream_t s) {
+                                    const double* scalars, int gauge_region, double* partial, hipStream_t s) {
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
-    allow_lds(k_xinv<T, Tout, kXThreads, MODE, RMAX>);
-    hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, MODE, RMAX>), dim3(x_grid(nb)), dim3(kXThreads), x_lds_bytes(a),
-                       s, S, u, a, shift, scalars, gauge_region, partial, nb, accumulate);
+    if constexpr (RMAX <= 16) {
+        if (x_full<RMAX>(a)) {
+            allow_lds<k_xinv<T, Tout, kXThreads, MODE, RMAX, true>>();
+            hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, MODE, RMAX, true>), dim3(x_grid(nb)), dim3(kXThreads),
+                               x_lds_bytes(a), s, S, u, a, shift, scalars, gauge_region, partial, nb);
+            return hipGetLastError();
+        }
+    }
+    {
+        allow_lds<k_xinv<T, Tout, kXThreads, MODE, RMAX, false>>();
+        hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, MODE, RMAX, false>), dim3(x_grid(nb)), dim3(kXThreads),
+                           x_lds_bytes(a), s, S, u, a, shift, scalars, gauge_region, partial, nb);
+    }
     return hipGetLastError();
 }
 
 template <typename T, typename Tout, int MODE>
 static hipError_t launch_xinv_any(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
-                                  const double* scalars, int gauge_region, double* partial, int accumulate,
-                                  hipStream_t s) {
+                                  const double* scalars, int gauge_region, double* partial, hipStream_t s) {
     if (a.nx <= 512)
-        return launch_xinv_shape<T, Tout, MODE, 8>(S, u, a, batch, shift, scalars, gauge_region, partial, accumulate,
-                                                   s);
+        return launch_xinv_shape<T, Tout, MODE, 8>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx <= 1024)
-        return launch_xinv_shape<T, Tout, MODE, 16>(S, u, a, batch, shift, scalars, gauge_region, partial,
-                                                    accumulate, s);
-    return launch_xinv_shape<T, Tout, MODE, 32>(S, u, a, batch, shift, scalars, gauge_region, partial, accumulate, s);
+        return launch_xinv_shape<T, Tout, MODE, 16>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
+    return launch_xinv_shape<T, Tout, MODE, 32>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
 }
 
 template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift, hipStream_t s) {
     return launch_xinv_any<T, Tout, XINV_STORE>(S, u, a, batch, shift, (const double*)nullptr, 0, (double*)nullptr,
-                                                0, s);
+                                                s);
 }
 
 hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float>& a, int batch,
                               const double* scalars, int gauge_region, double* partial, int accumulate,
                               hipStream_t s) {
     const double* shift = scalars + SC_COUNT + batch;   // cmean of the correction solve
-    return launch_xinv_any<float, double, XINV_UPDATE>(S, u, a, batch, shift, scalars, gauge_region, partial,
-                                                       accumulate, s);
+    if (accumulate)
+        return launch_xinv_any<float, double, XINV_UPDATE>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
+    return launch_xinv_any<float, double, XINV_FIRST>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
 }
 
 template hipError_t launch_xfwd<double, double>(const double*, cplx<double>*, double*, const XArgs<double>&, int,

@@ -302,12 +302,6 @@ constexpr int kSZ = 8;        // planes per chunk = wavefronts per workgroup
 constexpr int kSNy = 512;     // longest y line of the pipelined march
 constexpr int kSLdy = 576;    // work-buffer plane stride (>= padded_len(512))
 
-// Workgroup barrier that orders LDS accesses only: the wavefront's LDS
-// operations complete, then all wavefronts meet.  Unlike __syncthreads() it
-// does not wait for outstanding global loads, which the march keeps in flight
-// across barriers.  The memory clobber keeps the compiler from moving memory
-// accesses across it.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <typename T, bool FULL>
 __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
