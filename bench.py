@@ -118,6 +118,28 @@ def roofline_block(per, abytes, workload, dtype, ny):
                 bytes_per_launch=abytes[best], avg_launch_ms=round(k["avg_ms"], 5))
 
 
+def device_copy_bandwidth(reps=10):
+    """Read + write bandwidth of a plain 1 GiB device-to-device copy (torch copy_),
+    the practical ceiling for a kernel that streams its input once and its
+    output once."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+    b = torch.empty_like(a)
+    b.copy_(a)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / reps
+    nbytes = 2 * a.numel() * a.element_size()
+    del a, b
+    return nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(workload_name):
     """The oracle, timed on this host, on the same recipe at 256^3 (1/8 of the points)."""
     import numpy as np
@@ -186,6 +208,8 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 1 GiB device copies done")
         del a, b
+    copy_gbs = device_copy_bandwidth()
+    log(f"device copy (1 GiB read + 1 GiB write): {copy_gbs:.0f} GB/s")
 
     log(f"plan f64 {shape} {bc} batch {batch}")
     plan = Plan(shape, bc, h, dtype="f64", batch=batch)
@@ -214,6 +238,7 @@ def main():
         "config": {"workload": args.workload, "shape_zyx": list(shape), "bc": bc, "batch": batch,
                    "h": list(h)},
         "roofline": roofline_block(per, ab64, args.workload, "f64", shape[1]),
+        "device_copy_GBs": round(copy_gbs, 1),
         "solve_hbm_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
         "solve_hbm_frac": round(total_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         "kernels": kern,

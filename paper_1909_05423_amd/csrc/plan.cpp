@@ -288,6 +288,24 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
+// Spectral array layout.  z-major ([b][z][slot][y]): the workgroups of the z
+// march, one per slot, advance through z together, so at any moment they touch
+// one contiguous stretch of the array rather than one line in each of a few
+// hundred columns a power of two apart; the x kernels write and read whole
+// z planes either way.
+#ifndef PP_SPECTRAL_ZMAJOR
+#define PP_SPECTRAL_ZMAJOR 1
+#endif
+void spectral_strides(pp_plan p, long* sstride, long* zstride) {
+    if (PP_SPECTRAL_ZMAJOR) {
+        *sstride = p->ny;
+        *zstride = (long)p->slots * p->ny;
+    } else {
+        *sstride = (long)p->nz * p->ny;
+        *zstride = p->ny;
+    }
+}
+
 template <typename T> pp::XArgs<T> make_xargs(pp_plan p, unsigned char* ws) {
     pp::XArgs<T> a{};
     a.nx = p->nx;
@@ -297,6 +315,7 @@ template <typename T> pp::XArgs<T> make_xargs(pp_plan p, unsigned char* ws) {
     a.bx = p->bx;
     a.ty = p->ty;
     a.ldl = p->ldl;
+    spectral_strides(p, &a.sstride, &a.zstride);
     a.fx = p->fx;
     unsigned char* t = ws + p->o_tables;
     a.twx = reinterpret_cast<const cplx<T>*>(t + p->t_twx);
@@ -316,6 +335,7 @@ template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, 
     a.by = p->by;
     a.ldy = p->ldy;
     a.zb = p->zb;
+    spectral_strides(p, &a.sstride, &a.zstride);
     a.singular = p->singular ? 1 : 0;
     a.project = project ? 1 : 0;
     a.demean = demean ? 1 : 0;

@@ -45,6 +45,7 @@ template <typename T> struct XArgs {
     int bx;                  // boundary type along x (Bc)
     int ty;                  // rows per workgroup (even; ty/2 * nx <= kXElems)
     int ldl;                 // LDS line stride (padded_len(nx))
+    long sstride, zstride;   // spectral array: element (b, m, z, y) at b*slots*nz*ny + m*sstride + z*zstride + y
     FftDesc fx;              // radix plan for nx
     const cplx<T>* twx;      // exp(-2 pi i j / nx), j < nx
     const cplx<T>* mkx;      // exp(-i pi k / (2 nx)), k < nx
@@ -64,6 +65,7 @@ template <typename T> struct MidArgs {
     int singular;            // zero mode present (slot 0, entry 0, real part)
     int project;             // subtract the source mean from the zero-mode line
     int demean;              // report the mean of the zero-mode solution (subtracted by the x inverse)
+    long sstride, zstride;   // spectral array strides (as in XArgs)
     T scale;                 // hz^2 / (nx ny): all transform normalisations and the z-system scaling
     double hz2;              // hz^2 (projection constant = hz^2 * mean(f))
     FftDesc fy;

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                 const int ya = xb.y0 + 2 * j;
                 cplx<T> oa, ob;
                 column(m, j, oa, ob);
-                const size_t col = ((size_t)m * nz + xb.z) * ny;
+                const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
                 dstS[col + ya] = oa;
                 dstS[col + ya + 1] = ob;
             }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                 const int ya = xb.y0 + 2 * j, yb = ya + 1;
                 cplx<T> oa, ob;
                 column(m, j, oa, ob);
-                const size_t col = ((size_t)m * nz + xb.z) * ny;
+                const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
                 if (ya < ny) dstS[col + ya] = oa;
                 if (yb < ny) dstS[col + yb] = ob;
             }
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
             if (FULL) {
                 const int m = fdiv(i, inv_nl), j = i - m * nlines;
                 const int ya = xb.y0 + 2 * j;
-                const size_t col = ((size_t)m * nz + xb.z) * ny;
+                const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
                 sa[k] = srcS[col + ya];
                 sb[k] = srcS[col + ya + 1];
             } else {
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                 if (i < npair) {
                     const int m = fdiv(i, inv_nl), j = i - m * nlines;
                     const int ya = xb.y0 + 2 * j;
-                    const size_t col = ((size_t)m * nz + xb.z) * ny;
+                    const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
                     if (ya < ny) sa[k] = srcS[col + ya];
                     if (ya + 1 < ny) sb[k] = srcS[col + ya + 1];
                 }

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* twl = lds + zb * ldy;
     for (int i = tid; i < ny; i += NTH) twl[i] = a.twy[i];
-    cplx<T>* col = S + ((size_t)b * a.slots + m) * (size_t)nz * ny;
+    cplx<T>* col = S + (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride;
+    const size_t zs = (size_t)a.zstride;
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
     const bool sing = a.singular && (m == 0);
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             const LaneSlot ls = lane_slot(r, epl, inv_epl, wave, NW, lane);
-            if (r < ppw * epl && ls.l < nl && ls.y < ny) pre[r] = col[(size_t)(z0 + ls.l) * ny + ls.y];
+            if (r < ppw * epl && ls.l < nl && ls.y < ny) pre[r] = col[(size_t)(z0 + ls.l) * zs + ls.y];
         }
     };
 
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
                             cplx<T> dd = d[j];
                             if (sing && e == 0) dd.x -= proj;
                             prev = mk<T>((dd.x - prev.x) * w[j].x, (dd.y - prev.y) * w[j].y);
-                            col[(size_t)(zc + l) * ny + e] = prev;
+                            col[(size_t)(zc + l) * zs + e] = prev;
                         }
                     }
                 }
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
                 if (a.by != BC_P) pos = makhoul_pos(y, ny);
                 cplx<T> v = line[pad(pos)];
                 if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
-                col[(size_t)(zc + l) * ny + y] = v;
+                col[(size_t)(zc + l) * zs + y] = v;
             }
         }
     }
@@ -320,7 +321,8 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         twl[i] = a.twy[i];
         mkl[i] = a.mky[i];
     }
-    cplx<T>* col = S + ((size_t)b * a.slots + m) * (size_t)nz * ny;
+    cplx<T>* col = S + (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride;
+    const size_t zs = (size_t)a.zstride;
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
     const bool sing = a.singular && (m == 0);
@@ -339,15 +341,17 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     const cplx<T> wlast = a.wlast[(size_t)m * ny + ec];
 
     // reciprocal pivots of planes zc .. zc+7 for entry e (planes past the
-    // slot's rows read row 0 of the table, which always exists; the value then
-    // comes from winf / wlast)
+    // slot's rows read the first table element, which always exists; the value
+    // then comes from winf / wlast)
     cplx<T> pv[kSZ];
     const cplx<T>* wrows = a.wrows + ec;
     auto load_piv = [&](int zc) {
 #pragma unroll
         for (int l = 0; l < kSZ; ++l) {
             const int z = zc + l;
-            pv[l] = wrows[(size_t)((z < lmax) ? roff + z : 0) * ny];
+            // past the slot's rows every lane reads the same element, one cache line per wavefront
+            const cplx<T>* src = (z < lmax) ? wrows + (size_t)(roff + z) * ny : a.wrows;
+            pv[l] = *src;
         }
     };
     auto pivot = [&](int z, int l) -> cplx<T> {
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     // upward prefetch: elements y = lane + 64 k of plane zc + wave (clamped to the last plane)
     cplx<T> pre[EPL];
     auto load_plane = [&](int zc) {
-        const cplx<T>* src = col + (size_t)min(zc + wave, nz - 1) * ny;
+        const cplx<T>* src = col + (size_t)min(zc + wave, nz - 1) * zs;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
             const int y = lane + 64 * k;
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     // downward prefetch: entry e of planes zc .. zc+7 (clamped to the last plane)
     auto load_entry = [&](int zc) {
 #pragma unroll
-        for (int l = 0; l < kSZ; ++l) pre[l] = col[(size_t)min(zc + l, nz - 1) * ny + ec];
+        for (int l = 0; l < kSZ; ++l) pre[l] = col[(size_t)min(zc + l, nz - 1) * zs + ec];
     };
 
     // ------------------------------------------------------------- upward
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
                     cplx<T> d = cscale(work[l * kSLdy + pad(e)], scale);
                     if (sing && e == 0) d.x -= proj;
                     prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
-                    col[(size_t)z * ny + e] = prev;
+                    col[(size_t)z * zs + e] = prev;
                 }
             }
             st = prev;
@@ -503,7 +507,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
             }
             wave_lds_sync();
             wfft<EPL, true, T>(line, a.fy, twl, lane);
-            cplx<T>* dst = col + (size_t)(zc + wave) * ny;
+            cplx<T>* dst = col + (size_t)(zc + wave) * zs;
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 const int y = lane + 64 * k;
