@@ -110,6 +110,24 @@ size_t pp_plan_workspace_bytes(pp_plan p);
  * must not be modified between solves.  f is read only. */
 pp_status pp_solve(pp_plan p, const void* f, void* u, void* workspace, void* stream);
 
+/* Solve with non-homogeneous face values (section "Boundary Conditions":
+ * the part of each ghost value that does not depend on u moves to the
+ * right-hand side, so the boundary cells of a Dirichlet face solve with
+ * f - 2 g / h^2 and those of a Neumann face with f - g / h).
+ *   faces  array of 6 device pointers in the order x-, x+, y-, y+, z-, z+; each
+ *          is NULL (homogeneous face) or holds, per batch entry, the face's
+ *          values in C order: x faces [batch][nz][ny], y faces [batch][nz][nx],
+ *          z faces [batch][ny][nx], in the element type of f.  A Dirichlet face
+ *          carries the value of u on the face; a Neumann face the derivative of
+ *          u along the outward normal.  A periodic face must be NULL.
+ * faces itself may be NULL (same as pp_solve).  Face arrays are read only and
+ * must not overlap u or the workspace.  Otherwise as pp_solve.  In a singular
+ * problem the compatibility projection removes the mean of the lifted source,
+ * so Neumann fluxes and f need not balance.
+ * Errors: PP_ERR_ARG for a value on a periodic face or a misaligned face
+ * pointer; PP_ERR_ALIAS for a face overlapping u or the workspace. */
+pp_status pp_solve_bc(pp_plan p, const void* f, const void* const faces[6], void* u, void* workspace, void* stream);
+
 /* out = G^T g, the transpose of the linear map f -> u that pp_solve applies,
  * for dJ/df = G^T dJ/du.  Same array rules as pp_solve.  The transforms, the
  * z-systems (symmetric: equal off-diagonals) and the per-mode weights of the

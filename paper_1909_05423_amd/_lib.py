@@ -21,7 +21,7 @@ STATUS = {
 
 EXPORTED = [
     "pp_plan_create", "pp_plan_set_gauge", "pp_plan_set_refinement", "pp_plan_workspace_bytes",
-    "pp_solve", "pp_solve_adjoint", "pp_plan_last_info", "pp_plan_set_timing", "pp_plan_kernel_times",
+    "pp_solve", "pp_solve_bc", "pp_solve_adjoint", "pp_plan_last_info", "pp_plan_set_timing", "pp_plan_kernel_times",
     "pp_plan_destroy", "pp_status_string",
 ]
 
@@ -55,6 +55,8 @@ def load():
     lib.pp_plan_workspace_bytes.restype = ctypes.c_size_t
     lib.pp_solve.argtypes = [vp, vp, vp, vp, vp]
     lib.pp_solve.restype = i
+    lib.pp_solve_bc.argtypes = [vp, vp, ctypes.POINTER(vp), vp, vp, vp]
+    lib.pp_solve_bc.restype = i
     lib.pp_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.pp_solve_adjoint.restype = i
     lib.pp_plan_last_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(d)]

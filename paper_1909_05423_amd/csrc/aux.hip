@@ -87,7 +87,8 @@ hipError_t launch_finalize_update(const double* partial, int nper, int batch, do
     return hipGetLastError();
 }
 
-// r = scale * (f - c - L_h u) in double, stored as float (c: see ResidualArgs;
+// r = scale * (f - lift - c - L_h u) in double, stored as float (lift: the face
+// values of a non-homogeneous problem, see FaceArgs; c: see ResidualArgs;
 // removing it in double keeps the float image of r at the precision of the
 // small correction it carries).  L_h: the 7-point stencil
 // of Eq. 3 with the face ghost rules (periodic wrap; Dirichlet ghost = -u of
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
         const double lap = lx * a.ihx2 + ly * a.ihy2 + lz * a.ihz2;
         const size_t idx = base + (size_t)k * plane;
         double fi = f[idx];
+        if (a.has_faces) fi -= face_lift(a.faces, b, i, j, k, a.nx, a.ny, a.nz);
         if (a.proj == 1) fi -= mu;
         else if (a.proj == 2 && k == 0) fi -= (double)a.nz * mu;
         r[idx] = (float)((fi - lap) * scale);

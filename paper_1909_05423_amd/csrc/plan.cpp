@@ -400,7 +400,8 @@ int x_records(pp_plan p) {
 }
 
 template <typename T, typename Tio>
-pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStream_t s, bool project, bool demean) {
+pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStream_t s, bool project, bool demean,
+                    const pp::FaceArgs<Tio>* faces) {
     pp::XArgs<T> xa = make_xargs<T>(p, ws);
     pp::MidArgs<T> ma = make_midargs<T>(p, ws, project, demean);
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
@@ -409,7 +410,7 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
     const double npts = (double)p->nx * p->ny * p->nz;
     pp_status st;
     if ((st = mark(p, s, 0)) != PP_OK) return st;
-    PP_HIP((pp::launch_xfwd<T, Tio>(f, S, partial, xa, p->batch, s)));
+    PP_HIP((pp::launch_xfwd<T, Tio>(f, S, partial, xa, p->batch, faces, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
                                     sc + pp::SC_MAXF, s));
@@ -421,7 +422,7 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
 }
 
 pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, hipStream_t s, bool project,
-                      bool demean) {
+                      bool demean, const pp::FaceArgs<double>* faces) {
     pp::XArgs<float> xa = make_xargs<float>(p, ws);
     pp::MidArgs<float> ma = make_midargs<float>(p, ws, project, demean);
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
@@ -448,12 +449,16 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     ra.ihx2 = 1.0 / (p->h[0] * p->h[0]);
     ra.ihy2 = 1.0 / (p->h[1] * p->h[1]);
     ra.ihz2 = 1.0 / (p->h[2] * p->h[2]);
+    if (faces) {
+        ra.faces = *faces;
+        ra.has_faces = 1;
+    }
 
     pp_status st;
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_ir_init(sc, p->batch, s));
     if ((st = mark(p, s, 0)) != PP_OK) return st;
-    PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, s)));
+    PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, faces, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
                                     sc + pp::SC_MAXF, s));
@@ -471,7 +476,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         if ((st = mark(p, s, 3)) != PP_OK) return st;
         PP_HIP(pp::launch_residual(f, u, r, ra, sc, s));
         if ((st = mark(p, s, 0)) != PP_OK) return st;
-        PP_HIP((pp::launch_xfwd<float, float>(r, S, partial, xa, p->batch, s)));
+        PP_HIP((pp::launch_xfwd<float, float>(r, S, partial, xa, p->batch, nullptr, s)));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
         PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
         if ((st = mark(p, s, 1)) != PP_OK) return st;
@@ -499,7 +504,34 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     return PP_ERR_NOT_CONVERGED;
 }
 
-pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* stream, bool adjoint) {
+// Face-value block of a non-homogeneous solve.  Absent faces read from f with a
+// zero coefficient, so the kernels load every face unconditionally (f is at
+// least as large as any face array).
+template <typename Tin> pp::FaceArgs<Tin> face_args(pp_plan p, const void* f, const void* const* faces) {
+    pp::FaceArgs<Tin> fa{};
+    for (int i = 0; i < 6; ++i) {
+        const double hd = p->h[i / 2];
+        if (faces[i]) {
+            fa.g[i] = reinterpret_cast<const Tin*>(faces[i]);
+            fa.c[i] = (p->bc[i] == 'D') ? 2.0 / (hd * hd) : 1.0 / hd;
+        } else {
+            fa.g[i] = reinterpret_cast<const Tin*>(f);
+            fa.c[i] = 0.0;
+        }
+    }
+    return fa;
+}
+
+// Elements of face i per batch entry: x faces nz*ny, y faces nz*nx, z faces ny*nx.
+size_t face_elems(pp_plan p, int i) {
+    const int d = i / 2;
+    if (d == 0) return (size_t)p->nz * p->ny;
+    if (d == 1) return (size_t)p->nz * p->nx;
+    return (size_t)p->ny * p->nx;
+}
+
+pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* stream, bool adjoint,
+                   const void* const* faces = nullptr) {
     if (!p || !f || !u) return PP_ERR_ARG;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return PP_ERR_WORKSPACE;
     const size_t n = (size_t)p->nx * p->ny * p->nz * p->batch;
@@ -508,6 +540,18 @@ pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* str
     if (overlap(f, n * io, u, n * io) || overlap(u, n * io, workspace, p->ws_bytes) ||
         overlap(f, n * io, workspace, p->ws_bytes))
         return PP_ERR_ALIAS;
+    bool any_face = false;
+    if (faces) {
+        for (int i = 0; i < 6; ++i) {
+            if (!faces[i]) continue;
+            if (p->bc[i] == 'P') return PP_ERR_ARG;   // periodic faces carry no values
+            if (((uintptr_t)faces[i] % io) != 0) return PP_ERR_ARG;
+            const size_t nb = face_elems(p, i) * p->batch * io;
+            if (overlap(faces[i], nb, u, n * io) || overlap(faces[i], nb, workspace, p->ws_bytes))
+                return PP_ERR_ALIAS;
+            any_face = true;
+        }
+    }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
     if (p->bound_ws != workspace) {
@@ -533,12 +577,20 @@ pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* str
     p->last_rel = 0.0;
     p->last_projected = p->singular && project;
     switch (p->dtype) {
-        case PP_F64:
-            return run_plain<double, double>(p, (const double*)f, (double*)u, ws, s, project, demean);
-        case PP_F32:
-            return run_plain<float, float>(p, (const float*)f, (float*)u, ws, s, project, demean);
-        case PP_F32_REFINED:
-            return run_refined(p, (const double*)f, (double*)u, ws, s, project, demean);
+        case PP_F64: {
+            const pp::FaceArgs<double> fa = any_face ? face_args<double>(p, f, faces) : pp::FaceArgs<double>{};
+            return run_plain<double, double>(p, (const double*)f, (double*)u, ws, s, project, demean,
+                                             any_face ? &fa : nullptr);
+        }
+        case PP_F32: {
+            const pp::FaceArgs<float> fa = any_face ? face_args<float>(p, f, faces) : pp::FaceArgs<float>{};
+            return run_plain<float, float>(p, (const float*)f, (float*)u, ws, s, project, demean,
+                                           any_face ? &fa : nullptr);
+        }
+        case PP_F32_REFINED: {
+            const pp::FaceArgs<double> fa = any_face ? face_args<double>(p, f, faces) : pp::FaceArgs<double>{};
+            return run_refined(p, (const double*)f, (double*)u, ws, s, project, demean, any_face ? &fa : nullptr);
+        }
     }
     return PP_ERR_ARG;
 }
@@ -663,6 +715,11 @@ pp_status pp_solve(pp_plan p, const void* f, void* u, void* workspace, void* str
 
 pp_status pp_solve_adjoint(pp_plan p, const void* g, void* out, void* workspace, void* stream) {
     return dispatch(p, g, out, workspace, stream, true);
+}
+
+pp_status pp_solve_bc(pp_plan p, const void* f, const void* const faces[6], void* u, void* workspace,
+                      void* stream) {
+    return dispatch(p, f, u, workspace, stream, false, faces);
 }
 
 pp_status pp_plan_last_info(pp_plan p, int* ir_iters, double* removed_mean, double* final_rel_update) {

@@ -51,6 +51,40 @@ template <typename T> struct XArgs {
     const cplx<T>* mkx;      // exp(-i pi k / (2 nx)), k < nx
 };
 
+// Non-homogeneous face values, faces in the order x-, x+, y-, y+, z-, z+.  The
+// part of a ghost value that does not depend on u moves to the right-hand side
+// (section "Boundary Conditions"): the boundary cells of face i take
+// f - c_i g_i, with c = 2/h^2 for a Dirichlet value g and 1/h for a Neumann
+// outward derivative g.  g[i] is null for a homogeneous or periodic face.
+// Layout per batch entry (C order): x faces [nz][ny], y faces [nz][nx],
+// z faces [ny][nx].
+template <typename Tin> struct FaceArgs {
+    const Tin* g[6];
+    double c[6];
+};
+
+// Lift of the y and z face values at cell (i, j, k) of batch entry b (zero off those faces).
+template <typename Tin>
+__device__ __forceinline__ double face_lift_yz(const FaceArgs<Tin>& fa, int b, int i, int j, int k, int nx, int ny,
+                                               int nz) {
+    double l = 0.0;
+    if (j == 0 && fa.g[2]) l += fa.c[2] * (double)fa.g[2][((size_t)b * nz + k) * nx + i];
+    if (j == ny - 1 && fa.g[3]) l += fa.c[3] * (double)fa.g[3][((size_t)b * nz + k) * nx + i];
+    if (k == 0 && fa.g[4]) l += fa.c[4] * (double)fa.g[4][((size_t)b * ny + j) * nx + i];
+    if (k == nz - 1 && fa.g[5]) l += fa.c[5] * (double)fa.g[5][((size_t)b * ny + j) * nx + i];
+    return l;
+}
+
+// Lift of all face values at cell (i, j, k) of batch entry b (zero off the faces).
+template <typename Tin>
+__device__ __forceinline__ double face_lift(const FaceArgs<Tin>& fa, int b, int i, int j, int k, int nx, int ny,
+                                            int nz) {
+    double l = face_lift_yz(fa, b, i, j, k, nx, ny, nz);
+    if (i == 0 && fa.g[0]) l += fa.c[0] * (double)fa.g[0][((size_t)b * nz + k) * ny + j];
+    if (i == nx - 1 && fa.g[1]) l += fa.c[1] * (double)fa.g[1][((size_t)b * nz + k) * ny + j];
+    return l;
+}
+
 // Solution mode of the inverse x kernel.
 // XINV_UPDATE adds the correction to u; XINV_FIRST stores the first solution
 // of the refinement without reading u.
@@ -89,6 +123,8 @@ struct ResidualArgs {
     int bc[6];
     int proj;
     double ihx2, ihy2, ihz2;
+    FaceArgs<double> faces;  // non-homogeneous face values (all null: homogeneous)
+    int has_faces;
 };
 
 // --- launchers (return hipError_t of the launch) -----------------------------
@@ -97,8 +133,10 @@ struct ResidualArgs {
 int x_blocks(int ny, int ty, int nz, int batch);
 int x_grid(int nblocks);
 
+// faces: null, or the face values to lift into the source as it is read.
 template <typename T, typename Tin>
-hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch, hipStream_t s);
+hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+                       const FaceArgs<Tin>* faces, hipStream_t s);
 
 template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,

@@ -76,9 +76,10 @@ __device__ __forceinline__ double wave_max(double v) {
 // wavefront, ny a multiple of the block height) has no data-dependent branch
 // around a memory instruction, so that count is exact; the first block is
 // issued outside the loop so every pass through it sees the same sequence.
-template <typename T, typename Tin, int NTH, int RMAX, bool FULL>
+template <typename T, typename Tin, int NTH, int RMAX, bool FULL, bool FACES>
 __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
-                                              double* __restrict__ partial, XArgs<T> a, int nblocks) {
+                                              double* __restrict__ partial, XArgs<T> a, int nblocks,
+                                              FaceArgs<Tin> fa) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NW = NTH / 64;
     constexpr int PAIRS = RMAX / 2;   // FULL: column writes per thread, slots * nlines == NTH * PAIRS
@@ -100,8 +101,18 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
 
     // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
     Tin ra[RMAX], rb[RMAX];
+    // FULL with face values: the x-face values of this wave's two rows, fetched
+    // with them (the lanes holding columns 0 and nx-1 use them)
+    Tin gx[FACES && FULL ? 4 : 1];
     auto fetch = [&](int blk) {
         const XBlock xb = x_block(blk, nyb, nz, ty);
+        if constexpr (FACES && FULL) {
+            const size_t row = ((size_t)xb.b * nz + xb.z) * ny + xb.y0 + 2 * wave;
+            gx[0] = fa.g[0][row];
+            gx[1] = fa.g[0][row + 1];
+            gx[2] = fa.g[1][row];
+            gx[3] = fa.g[1][row + 1];
+        }
         const Tin* src = f + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
@@ -178,15 +189,38 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
         }
         lds_barrier();   // the previous column writes are done reading the lines (and the twiddles are in)
         // 1. registers -> own packed lines (row 2j real part, row 2j+1 imaginary part),
-        //    pre-processed for the x transform; wavefront sums of the source
+        //    pre-processed for the x transform; face values lifted into the source;
+        //    wavefront sums of the (lifted) source
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             const int p = FULL ? 0 : fdiv(r, inv_epl);
             const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
             if (FULL || (j < nlines && n < nx)) {
-                acc += (double)ra[r] + (double)rb[r];
-                amax = fmax(amax, fmax(fabs((double)ra[r]), fabs((double)rb[r])));
-                T va = (T)ra[r], vb = (T)rb[r];
+                double la = 0.0, lb = 0.0;   // lift of rows ya, ya + 1 at column n
+                if constexpr (FACES) {
+                    const int ya = xb.y0 + 2 * j;
+                    if constexpr (FULL) {
+                        if (n == 0) {
+                            la += fa.c[0] * (double)gx[0];
+                            lb += fa.c[0] * (double)gx[1];
+                        }
+                        if (n == nx - 1) {
+                            la += fa.c[1] * (double)gx[2];
+                            lb += fa.c[1] * (double)gx[3];
+                        }
+                        if (ya == 0 || ya + 1 == ny - 1 || xb.z == 0 || xb.z == nz - 1) {
+                            la += face_lift_yz(fa, xb.b, n, ya, xb.z, nx, ny, nz);
+                            lb += face_lift_yz(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
+                        }
+                    } else {
+                        if (ya < ny) la = face_lift(fa, xb.b, n, ya, xb.z, nx, ny, nz);
+                        if (ya + 1 < ny) lb = face_lift(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
+                    }
+                }
+                const double fa_ = (double)ra[r] - la, fb_ = (double)rb[r] - lb;
+                acc += fa_ + fb_;
+                amax = fmax(amax, fmax(fabs(fa_), fabs(fb_)));
+                T va = (T)fa_, vb = (T)fb_;
                 int pos = n;
                 if (a.bx != BC_P) {
                     pos = makhoul_pos(n, nx);
@@ -500,31 +534,40 @@ template <int RMAX, typename T> static bool x_full(const XArgs<T>& a) {
     return RMAX <= 16 && a.nx == 64 * RMAX && a.ty == 2 * kXWaves && a.ny % a.ty == 0;
 }
 
-template <typename T, typename Tin, int RMAX>
+template <typename T, typename Tin, int RMAX, bool FACES>
 static hipError_t launch_xfwd_shape(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
-                                    hipStream_t s) {
+                                    const FaceArgs<Tin>& fa, hipStream_t s) {
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
     if constexpr (RMAX <= 16) {
         if (x_full<RMAX>(a)) {
-            allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, true>>();
-            hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, true>), dim3(x_grid(nb)), dim3(kXThreads),
-                               x_lds_bytes(a), s, f, S, partial, a, nb);
+            allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, true, FACES>>();
+            hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, true, FACES>), dim3(x_grid(nb)), dim3(kXThreads),
+                               x_lds_bytes(a), s, f, S, partial, a, nb, fa);
             return hipGetLastError();
         }
     }
     {
-        allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, false>>();
-        hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, false>), dim3(x_grid(nb)), dim3(kXThreads),
-                           x_lds_bytes(a), s, f, S, partial, a, nb);
+        allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, false, FACES>>();
+        hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, false, FACES>), dim3(x_grid(nb)), dim3(kXThreads),
+                           x_lds_bytes(a), s, f, S, partial, a, nb, fa);
     }
     return hipGetLastError();
 }
 
+template <typename T, typename Tin, bool FACES>
+static hipError_t launch_xfwd_any(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+                                  const FaceArgs<Tin>& fa, hipStream_t s) {
+    if (a.nx <= 512) return launch_xfwd_shape<T, Tin, 8, FACES>(f, S, partial, a, batch, fa, s);
+    if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, 16, FACES>(f, S, partial, a, batch, fa, s);
+    return launch_xfwd_shape<T, Tin, 32, FACES>(f, S, partial, a, batch, fa, s);
+}
+
 template <typename T, typename Tin>
-hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch, hipStream_t s) {
-    if (a.nx <= 512) return launch_xfwd_shape<T, Tin, 8>(f, S, partial, a, batch, s);
-    if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, 16>(f, S, partial, a, batch, s);
-    return launch_xfwd_shape<T, Tin, 32>(f, S, partial, a, batch, s);
+hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+                       const FaceArgs<Tin>* faces, hipStream_t s) {
+    if (faces) return launch_xfwd_any<T, Tin, true>(f, S, partial, a, batch, *faces, s);
+    const FaceArgs<Tin> none{};
+    return launch_xfwd_any<T, Tin, false>(f, S, partial, a, batch, none, s);
 }
 
 template <typename T, typename Tout, int MODE, int RMAX>
@@ -573,11 +616,11 @@ hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float
 }
 
 template hipError_t launch_xfwd<double, double>(const double*, cplx<double>*, double*, const XArgs<double>&, int,
-                                                hipStream_t);
+                                                const FaceArgs<double>*, hipStream_t);
 template hipError_t launch_xfwd<float, float>(const float*, cplx<float>*, double*, const XArgs<float>&, int,
-                                              hipStream_t);
+                                              const FaceArgs<float>*, hipStream_t);
 template hipError_t launch_xfwd<float, double>(const double*, cplx<float>*, double*, const XArgs<float>&, int,
-                                               hipStream_t);
+                                               const FaceArgs<double>*, hipStream_t);
 template hipError_t launch_xinv<double, double>(const cplx<double>*, double*, const XArgs<double>&, int,
                                                 const double*, hipStream_t);
 template hipError_t launch_xinv<float, float>(const cplx<float>*, float*, const XArgs<float>&, int, const double*,

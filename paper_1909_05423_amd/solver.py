@@ -85,9 +85,41 @@ class Plan:
         _lib.check(status, what)
         return out
 
-    def solve(self, f, out=None):
-        """u with L_h u = f (see include/ppsolve.h for the zero-mode gauge)."""
-        return self._run(_lib.load().pp_solve, f, out, "pp_solve")
+    def face_shape(self, i):
+        """Shape of the value array of face i (x-, x+, y-, y+, z-, z+)."""
+        nz, ny, nx = self.shape
+        dims = [(nz, ny), (nz, ny), (nz, nx), (nz, nx), (ny, nx), (ny, nx)][i]
+        return (self.batch,) + dims
+
+    def solve(self, f, out=None, faces=None):
+        """u with L_h u = f (see include/ppsolve.h for the zero-mode gauge).
+
+        faces: optional sequence of six tensors or None (x-, x+, y-, y+, z-, z+):
+        Dirichlet face values or Neumann outward derivatives, each of shape
+        face_shape(i) (the batch axis may be dropped for batch 1), in f's dtype,
+        on f's device.  Periodic faces take None."""
+        if faces is None:
+            return self._run(_lib.load().pp_solve, f, out, "pp_solve")
+        if len(faces) != 6:
+            raise ValueError("faces must hold six entries (x-, x+, y-, y+, z-, z+)")
+        ptrs = (ctypes.c_void_p * 6)()
+        keep = []
+        for i, g in enumerate(faces):
+            if g is None:
+                continue
+            full = self.face_shape(i)
+            if tuple(g.shape) != full and not (self.batch == 1 and tuple(g.shape) == full[1:]):
+                raise ValueError(f"face {i} must have shape {full}, got {tuple(g.shape)}")
+            if g.dtype != self.torch_dtype or g.device != self.workspace.device or not g.is_contiguous():
+                raise ValueError(f"face {i} must be a contiguous {self.torch_dtype} tensor on {self.workspace.device}")
+            ptrs[i] = g.data_ptr()
+            keep.append(g)
+        lib = _lib.load()
+
+        def call(plan, src, dst, ws, stream):
+            return lib.pp_solve_bc(plan, src, ptrs, dst, ws, stream)
+
+        return self._run(call, f, out, "pp_solve_bc")
 
     def adjoint(self, g, out=None):
         """G^T g for the map G: f -> u of solve()."""

@@ -108,3 +108,22 @@ def test_argument_errors_before_any_gpu_call(lib):
     lib.pp_plan_destroy(p)
     for code in range(-8, 1):
         assert lib.pp_status_string(code)
+
+
+def test_face_argument_errors_before_any_gpu_call(lib):
+    st, p = _create(lib, 8, 8, 8, "PPNNDN")
+    assert st == 0
+    f = ctypes.c_void_p(0x100000)
+    u = ctypes.c_void_p(0x200000)
+    ws = ctypes.c_void_p(0x400000)
+    faces = (ctypes.c_void_p * 6)()
+    faces[0] = 0x500000                                                      # a value on a periodic face
+    assert lib.pp_solve_bc(p, f, faces, u, ws, None) == -1
+    faces[0] = None
+    faces[2] = 0x500004                                                      # misaligned
+    assert lib.pp_solve_bc(p, f, faces, u, ws, None) == -1
+    faces[2] = 0x200000 + 8 * 64                                             # inside u
+    assert lib.pp_solve_bc(p, f, faces, u, ws, None) == -4
+    faces[2] = 0x400000 + 256                                                # inside the workspace
+    assert lib.pp_solve_bc(p, f, faces, u, ws, None) == -4
+    lib.pp_plan_destroy(p)
