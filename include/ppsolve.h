@@ -46,7 +46,7 @@ typedef struct pp_plan_s* pp_plan;
 typedef enum { PP_F64 = 0, PP_F32 = 1, PP_F32_REFINED = 2 } pp_dtype;
 
 /* Treatment of the singular zero mode (pure Neumann/periodic x and y with
- * Neumann on both z faces); ignored for non-singular problems.
+ * Neumann or periodic z faces); ignored for non-singular problems.
  *   PP_GAUGE_MEAN     subtract the volume mean of f (the alternative the
  *                     "Well-posedness" section names), pin, then shift u to
  *                     zero volume mean.  Unique; the solve operator is symmetric.
@@ -61,7 +61,7 @@ typedef enum {
     PP_OK = 0,
     PP_ERR_ARG = -1,           /* null pointer, non-positive size/spacing/batch, bad enum */
     PP_ERR_BC = -2,            /* bc char not in {P,D,N}; x or y faces of different types;
-                                  periodic z (not supported) */
+                                  one z face periodic and the other not */
     PP_ERR_SIZE = -3,          /* nx or ny has a prime factor other than 2 and 3, or exceeds
                                   the on-chip line limit (2048), or nz * batch > 65535 */
     PP_ERR_ALIAS = -4,         /* u (or out) overlaps f (or g) or the workspace */
@@ -79,7 +79,9 @@ typedef enum {
  *               ghost cell by linear extrapolation), 'N' homogeneous Neumann
  *               (zero flux).  The two x faces share a type, as do the two y
  *               faces (Table eig lists only PP, NN, DD); z faces are D or N,
- *               each independently.
+ *               each independently, or both P (periodic z: each z-system is
+ *               cyclic and is solved through the Sherman-Morrison splitting of
+ *               the Thomas subsection; needs nz >= 3, else PP_ERR_SIZE).
  *   h           spacings (hx, hy, hz) > 0.
  *   dtype       see pp_dtype.  batch: independent right-hand sides, >= 1.
  * On success *out holds a plan to release with pp_plan_destroy.  The gauge

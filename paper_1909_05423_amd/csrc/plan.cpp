@@ -44,6 +44,9 @@ struct pp_plan_s {
     // tables (uploaded into the workspace)
     std::vector<unsigned char> blob;
     size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
+    // periodic z (Sherman-Morrison)
+    size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
+           t_invgam = 0;
     size_t table_rows = 0;
     // workspace layout (byte offsets)
     size_t o_scalars = 0, o_partial = 0, o_tables = 0, o_S = 0, o_r = 0, ws_bytes = 0;
@@ -146,17 +149,89 @@ template <typename T> struct Emit {
 // Reciprocal pivots of one z line.  body = w_0 .. w_{nz-2} until the value
 // stops changing; wl = w_{nz-1}; tail = first index from which the rounded
 // body value equals the rounded value at nz-2.
+//
+// Periodic z (Thomas subsection: the cyclic system by Sherman-Morrison).  With
+// gamma = -b the cyclic matrix is T' + v v'^T, v = (gamma, 0, .., 0, 1),
+// v' = (1, 0, .., 0, 1/gamma), where T' is tridiagonal with first diagonal
+// b - gamma = 2b and last diagonal b - 1/gamma.  Its solution is
+// u = y - c q with y = T'^{-1} d, q = T'^{-1} v and
+// c = (y_0 + y_{n-1}/gamma) / (1 + q_0 + q_{n-1}/gamma).  The kernels eliminate
+// with the pivots of T'; y_{n-1} is the last eliminated value, and
+// y_0 = sum_z alpha_z d_z with alpha = T'^{-1} e_0 (T' is symmetric), so c is
+// known when the march turns; on the way down q_z = qp_z - w_z q_{z+1} from
+// the forward-eliminated qp = (v after elimination).  alpha and qp decay
+// geometrically away from z = 0 and are stored up to where they fall below
+// 2^-60 of their largest value.  The pinned zero-mode line of a singular
+// problem (u_0 = 0, section "Well-posedness") is an ordinary tridiagonal
+// system and keeps alpha = qp = 0, 1/den = 0, so c = 0.
 template <typename T> struct Line {
     std::vector<T> body;
     T winf = 0, wlast = 0;
     int tail = 0;
+    std::vector<T> alpha, qp;       // periodic z only
+    T qlast = 0, inv_den = 0, inv_gamma = 0;
 };
+
+template <typename T> static int significant_prefix(const std::vector<double>& v) {
+    double mx = 0.0;
+    for (double x : v) mx = std::max(mx, std::fabs(x));
+    int L = (int)v.size();
+    while (L > 0 && std::fabs(v[L - 1]) <= mx * 0x1p-60) --L;
+    return L;
+}
+
+template <typename T> void periodic_extras(double bmid, int nz, const std::vector<double>& w, Line<T>* out) {
+    const double gamma = -bmid;
+    std::vector<double> qp(nz), q(nz), ap(nz), al(nz);
+    qp[0] = gamma * w[0];
+    ap[0] = w[0];
+    for (int z = 1; z < nz; ++z) {
+        const double vz = (z == nz - 1) ? 1.0 : 0.0;
+        qp[z] = (vz - qp[z - 1]) * w[z];
+        ap[z] = (0.0 - ap[z - 1]) * w[z];
+    }
+    q[nz - 1] = qp[nz - 1];
+    al[nz - 1] = ap[nz - 1];
+    for (int z = nz - 2; z >= 0; --z) {
+        q[z] = qp[z] - w[z] * q[z + 1];
+        al[z] = ap[z] - w[z] * al[z + 1];
+    }
+    out->qlast = (T)qp[nz - 1];
+    out->inv_gamma = (T)(1.0 / gamma);
+    out->inv_den = (T)(1.0 / (1.0 + q[0] + q[nz - 1] / gamma));
+    std::vector<double> qbody(qp.begin(), qp.end() - 1);   // the last value is qlast
+    const int Lq = significant_prefix<T>(qbody);
+    const int La = significant_prefix<T>(al);
+    out->qp.assign(qbody.begin(), qbody.begin() + Lq);
+    out->alpha.assign(al.begin(), al.begin() + La);
+}
 
 template <typename T>
 void pivots(double lam, int nz, double hz, int bz0, int bz1, bool pinned, Line<T>* out) {
     const double bmid = -2.0 + hz * hz * lam;
+    out->alpha.clear();
+    out->qp.clear();
+    out->qlast = out->inv_den = out->inv_gamma = 0;
+    if (bz0 == pp::BC_P && !pinned) {
+        // T' of the Sherman-Morrison splitting (nz >= 3): first diagonal 2b, last b + 1/b
+        std::vector<double> w(nz);
+        w[0] = 1.0 / (2.0 * bmid);
+        for (int z = 1; z < nz - 1; ++z) w[z] = 1.0 / (bmid - w[z - 1]);
+        w[nz - 1] = 1.0 / ((bmid + 1.0 / bmid) - w[nz - 2]);
+        periodic_extras<T>(bmid, nz, w, out);
+        out->wlast = (T)w[nz - 1];
+        out->winf = (T)w[nz - 2];
+        int L = nz - 1;
+        while (L > 0 && (T)w[L - 1] == out->winf) --L;
+        out->tail = L;
+        out->body.resize(L);
+        for (int i = 0; i < L; ++i) out->body[i] = (T)w[i];
+        return;
+    }
+    // the pinned zero mode of a periodic z direction: rows 1..n-1 with u_0 = 0,
+    // interior diagonal also in the last row (its wrap-around neighbour is u_0)
     const double d0 = (bz0 == pp::BC_D) ? -1.0 : 1.0;
-    const double d1 = (bz1 == pp::BC_D) ? -1.0 : 1.0;
+    const double d1 = (bz1 == pp::BC_P) ? 0.0 : (bz1 == pp::BC_D) ? -1.0 : 1.0;
     out->body.clear();
     if (nz == 1) {
         out->wlast = pinned ? T(0) : (T)(1.0 / (bmid + d0 + d1));
@@ -281,6 +356,45 @@ template <typename T> void build_tables(pp_plan p) {
             }
         }
     }
+    if (p->bz0 != pp::BC_P) return;
+    // periodic z: Sherman-Morrison rows (alpha, qp) per slot, and per-entry scalars
+    auto emit_rows = [&](std::vector<T> Line<T>::*vec, size_t* t_off, size_t* t_len, size_t* t_rows) {
+        std::vector<int> off(slots), len(slots);
+        size_t nrows = 0;
+        for (int m = 0; m < slots; ++m) {
+            int L = 0;
+            for (const Line<T>& ln : lines[m]) L = std::max(L, (int)(ln.*vec).size());
+            off[m] = (int)nrows;
+            len[m] = L;
+            nrows += L;
+        }
+        *t_off = em.put(sizeof(int) * slots);
+        std::memcpy(p->blob.data() + *t_off, off.data(), sizeof(int) * slots);
+        *t_len = em.put(sizeof(int) * slots);
+        std::memcpy(p->blob.data() + *t_len, len.data(), sizeof(int) * slots);
+        *t_rows = em.put(sizeof(T) * 2 * std::max<size_t>(nrows, 1) * ny);
+        T* rr = reinterpret_cast<T*>(p->blob.data() + *t_rows);
+        for (int m = 0; m < slots; ++m)
+            for (int z = 0; z < len[m]; ++z)
+                for (int e = 0; e < ny; ++e)
+                    for (int part = 0; part < 2; ++part) {
+                        const std::vector<T>& v = lines[m][(size_t)e * 2 + part].*vec;
+                        rr[((size_t)(off[m] + z) * ny + e) * 2 + part] = (z < (int)v.size()) ? v[z] : T(0);
+                    }
+    };
+    emit_rows(&Line<T>::alpha, &p->t_aoff, &p->t_alen, &p->t_arows);
+    emit_rows(&Line<T>::qp, &p->t_qoff, &p->t_qlen, &p->t_qrows);
+    auto emit_scalar = [&](T Line<T>::*field, size_t* t) {
+        *t = em.put(sizeof(T) * 2 * (size_t)slots * ny);
+        T* v = reinterpret_cast<T*>(p->blob.data() + *t);
+        for (int m = 0; m < slots; ++m)
+            for (int e = 0; e < ny; ++e)
+                for (int part = 0; part < 2; ++part)
+                    v[((size_t)m * ny + e) * 2 + part] = lines[m][(size_t)e * 2 + part].*field;
+    };
+    emit_scalar(&Line<T>::qlast, &p->t_qlast);
+    emit_scalar(&Line<T>::inv_den, &p->t_invden);
+    emit_scalar(&Line<T>::inv_gamma, &p->t_invgam);
 }
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -350,6 +464,18 @@ template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, 
     a.wrows = reinterpret_cast<const cplx<T>*>(t + p->t_wrows);
     a.winf = reinterpret_cast<const cplx<T>*>(t + p->t_winf);
     a.wlast = reinterpret_cast<const cplx<T>*>(t + p->t_wlast);
+    a.zper = (p->bz0 == pp::BC_P) ? 1 : 0;
+    if (a.zper) {
+        a.aoff = reinterpret_cast<const int*>(t + p->t_aoff);
+        a.alen = reinterpret_cast<const int*>(t + p->t_alen);
+        a.arows = reinterpret_cast<const cplx<T>*>(t + p->t_arows);
+        a.qoff = reinterpret_cast<const int*>(t + p->t_qoff);
+        a.qlen = reinterpret_cast<const int*>(t + p->t_qlen);
+        a.qrows = reinterpret_cast<const cplx<T>*>(t + p->t_qrows);
+        a.qlast = reinterpret_cast<const cplx<T>*>(t + p->t_qlast);
+        a.inv_den = reinterpret_cast<const cplx<T>*>(t + p->t_invden);
+        a.inv_gamma = reinterpret_cast<const cplx<T>*>(t + p->t_invgam);
+    }
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
     a.mu = sc + pp::SC_COUNT + 3 * p->batch;
     a.cmean = sc + pp::SC_COUNT + p->batch;
@@ -614,7 +740,8 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         if (code[i] < 0) return PP_ERR_BC;
     }
     if (code[0] != code[1] || code[2] != code[3]) return PP_ERR_BC;
-    if (code[4] == pp::BC_P || code[5] == pp::BC_P) return PP_ERR_BC;
+    if ((code[4] == pp::BC_P) != (code[5] == pp::BC_P)) return PP_ERR_BC;   // periodic z needs both faces
+    if (code[4] == pp::BC_P && nz < 3) return PP_ERR_SIZE;                     // Sherman-Morrison splitting
     if (!factor23(nx) || !factor23(ny)) return PP_ERR_SIZE;
     if (nx > pp::kMaxLine || ny > pp::kMaxLine || ny > pp::kZThreads * pp::kZOwned) return PP_ERR_SIZE;
     if ((long long)nz * batch > 65535) return PP_ERR_SIZE;
@@ -632,7 +759,8 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     p->by = code[2];
     p->bz0 = code[4];
     p->bz1 = code[5];
-    p->singular = (p->bx != pp::BC_D) && (p->by != pp::BC_D) && p->bz0 == pp::BC_N && p->bz1 == pp::BC_N;
+    p->singular = (p->bx != pp::BC_D) && (p->by != pp::BC_D) &&
+                  ((p->bz0 == pp::BC_N && p->bz1 == pp::BC_N) || p->bz0 == pp::BC_P);
     p->slots = (nx + 1) / 2;
     const bool f64 = (dtype == PP_F64);
     p->elem = f64 ? sizeof(cplx<double>) : sizeof(cplx<float>);

@@ -110,6 +110,12 @@ template <typename T> struct MidArgs {
     const cplx<T>* wrows;    // [row][ny] (w_re, w_im) reciprocal pivots
     const cplx<T>* winf;     // [slot][ny] converged reciprocal pivot
     const cplx<T>* wlast;    // [slot][ny] reciprocal pivot of the last row
+    // periodic z (Sherman-Morrison, see the plan code): per slot, rows of
+    // alpha = first row of the inverse of the split matrix and of the
+    // forward-eliminated rank-one vector; per entry its last value, 1/den, 1/gamma
+    int zper;
+    const int *aoff, *alen, *qoff, *qlen;
+    const cplx<T> *arows, *qrows, *qlast, *inv_den, *inv_gamma;
     const double* mu;        // [batch] source means
     double* cmean;           // [batch] mean of the zero-mode solution line (output)
 };

@@ -91,12 +91,21 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 
     // owned z-recurrence entries e = tid + q * NTH; converged and last-row pivots in registers
     cplx<T> st[OWN], winf[OWN], wlast[OWN];
+    // periodic z (Sherman-Morrison; see k_zpipe): y_0 accumulator, correction, q_{z+1}
+    cplx<T> y0[OWN], corr[OWN], qn[OWN];
+    const bool zper = a.zper != 0;
+    const int alen = zper ? a.alen[m] : 0, aoff = zper ? a.aoff[m] : 0;
+    const int qlen = zper ? a.qlen[m] : 0, qoff = zper ? a.qoff[m] : 0;
 #pragma unroll
     for (int q = 0; q < OWN; ++q) {
         const int e = tid + q * NTH;
         st[q] = mk<T>(T(0), T(0));
         winf[q] = st[q];
         wlast[q] = st[q];
+        y0[q] = st[q];
+        corr[q] = st[q];
+        qn[q] = st[q];
+        if (zper && e < ny) qn[q] = a.qlast[(size_t)m * ny + e];
         if (e < ny) {
             winf[q] = a.winf[(size_t)m * ny + e];
             wlast[q] = a.wlast[(size_t)m * ny + e];
@@ -187,6 +196,11 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
                         if (l < nl) {
                             cplx<T> dd = d[j];
                             if (sing && e == 0) dd.x -= proj;
+                            if (zper && zc + l < alen) {
+                                const cplx<T> al = a.arows[(size_t)(aoff + zc + l) * ny + e];
+                                y0[q].x += al.x * dd.x;
+                                y0[q].y += al.y * dd.y;
+                            }
                             prev = mk<T>((dd.x - prev.x) * w[j].x, (dd.y - prev.y) * w[j].y);
                             col[(size_t)(zc + l) * zs + e] = prev;
                         }
@@ -200,7 +214,15 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 
     // ----------------------------------------------------------- downward
 #pragma unroll
-    for (int q = 0; q < OWN; ++q) st[q] = mk<T>(T(0), T(0));
+    for (int q = 0; q < OWN; ++q) {
+        const int e = tid + q * NTH;
+        if (zper && e < ny) {
+            // st is y_{n-1}, the last eliminated value
+            const cplx<T> ig = a.inv_gamma[(size_t)m * ny + e], id = a.inv_den[(size_t)m * ny + e];
+            corr[q] = mk<T>((y0[q].x + st[q].x * ig.x) * id.x, (y0[q].y + st[q].y * ig.y) * id.y);
+        }
+        st[q] = mk<T>(T(0), T(0));
+    }
     double csum = 0.0;
     fetch((nchunks - 1) * zb, nz - (nchunks - 1) * zb);
     for (int c = nchunks - 1; c >= 0; --c) {
@@ -234,8 +256,18 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
                         const int l = l1 - j;
                         if (l >= 0) {
                             nxt = mk<T>(dp[j].x - w[j].x * nxt.x, dp[j].y - w[j].y * nxt.y);
-                            lds[l * ldy + pad(e)] = nxt;
-                            if (sing && e == 0) csum += (double)nxt.x;
+                            cplx<T> un = nxt;
+                            if (zper) {
+                                const int z = zc + l;
+                                if (z != nz - 1) {
+                                    const cplx<T> qp = (z < qlen) ? a.qrows[(size_t)(qoff + z) * ny + e]
+                                                                  : mk<T>(T(0), T(0));
+                                    qn[q] = mk<T>(qp.x - w[j].x * qn[q].x, qp.y - w[j].y * qn[q].y);
+                                }
+                                un = mk<T>(nxt.x - corr[q].x * qn[q].x, nxt.y - corr[q].y * qn[q].y);
+                            }
+                            lds[l * ldy + pad(e)] = un;
+                            if (sing && e == 0) csum += (double)un.x;
                         }
                     }
                 }
@@ -304,7 +336,7 @@ constexpr int kSNy = 512;     // longest y line of the pipelined march
 constexpr int kSLdy = 576;    // work-buffer plane stride (>= padded_len(512))
 
 
-template <typename T, bool FULL>
+template <typename T, bool FULL, bool PERZ>
 __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
     __shared__ __align__(16) cplx<T> work[kSZ * kSLdy];
     __shared__ __align__(16) cplx<T> twl[kSNy];
@@ -339,6 +371,18 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     const int ec = live ? e : 0;
     const cplx<T> winf = a.winf[(size_t)m * ny + ec];
     const cplx<T> wlast = a.wlast[(size_t)m * ny + ec];
+    // periodic z: y_0 accumulated on the way up, the correction c = (y_0 +
+    // y_{n-1}/gamma)/den at the turn, and q_z rebuilt on the way down (the
+    // Sherman-Morrison rows decay from z = 0, so only the first chunks read them)
+    cplx<T> y0 = mk<T>(T(0), T(0)), corr = y0, qnext = y0;
+    int alen = 0, aoff = 0, qlen = 0, qoff = 0;
+    if constexpr (PERZ) {
+        alen = a.alen[m];
+        aoff = a.aoff[m];
+        qlen = a.qlen[m];
+        qoff = a.qoff[m];
+        qnext = a.qlast[(size_t)m * ny + ec];
+    }
 
     // reciprocal pivots of planes zc .. zc+7 for entry e (planes past the
     // slot's rows read the first table element, which always exists; the value
@@ -430,6 +474,14 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         lds_barrier();
         // forward elimination over the chunk; eliminated right-hand sides go to HBM
         if (live) {
+            cplx<T> al[PERZ ? kSZ : 1];
+            if constexpr (PERZ) {
+                if (zc < alen) {
+#pragma unroll
+                    for (int l = 0; l < kSZ; ++l)
+                        al[l] = (zc + l < alen) ? a.arows[(size_t)(aoff + zc + l) * ny + ec] : mk<T>(T(0), T(0));
+                }
+            }
             cplx<T> prev = st;
 #pragma unroll
             for (int l = 0; l < kSZ; ++l) {
@@ -438,6 +490,12 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
                     const cplx<T> w = pivot(z, l);
                     cplx<T> d = cscale(work[l * kSLdy + pad(e)], scale);
                     if (sing && e == 0) d.x -= proj;
+                    if constexpr (PERZ) {
+                        if (zc < alen) {
+                            y0.x += al[l].x * d.x;
+                            y0.y += al[l].y * d.y;
+                        }
+                    }
                     prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
                     col[(size_t)z * zs + e] = prev;
                 }
@@ -455,6 +513,11 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     // the top chunk's eliminated right-hand sides were stored by this thread
     // (same entry, same addresses): read them back in program order
     load_entry(last);
+    if constexpr (PERZ) {
+        // st is y_{n-1}, the last eliminated value
+        const cplx<T> ig = a.inv_gamma[(size_t)m * ny + ec], id = a.inv_den[(size_t)m * ny + ec];
+        corr = mk<T>((y0.x + st.x * ig.x) * id.x, (y0.y + st.y * ig.y) * id.y);
+    }
     st = mk<T>(T(0), T(0));
     double csum = 0.0;
     auto down_chunk = [&](int c) {
@@ -463,6 +526,14 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         lds_barrier();   // the previous inverse transforms are done with the work buffer
         // back substitution over the chunk, from registers into the work buffer
         if (live) {
+            cplx<T> qv[PERZ ? kSZ : 1];
+            if constexpr (PERZ) {
+                if (zc < qlen) {
+#pragma unroll
+                    for (int l = 0; l < kSZ; ++l)
+                        qv[l] = (zc + l < qlen) ? a.qrows[(size_t)(qoff + zc + l) * ny + ec] : mk<T>(T(0), T(0));
+                }
+            }
             cplx<T> nxt = st;
 #pragma unroll
             for (int j = 0; j < kSZ; ++j) {
@@ -472,8 +543,17 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
                     const cplx<T> w = pivot(z, l);
                     const cplx<T> dp = pre[l];
                     nxt = mk<T>(dp.x - w.x * nxt.x, dp.y - w.y * nxt.y);
-                    work[l * kSLdy + pad(e)] = nxt;
-                    if (sing && e == 0) csum += (double)nxt.x;
+                    cplx<T> un = nxt;
+                    if constexpr (PERZ) {
+                        // q_z of the rank-one vector, then u_z = y_z - c q_z
+                        if (z != nz - 1) {
+                            const cplx<T> qp = (zc < qlen) ? qv[l] : mk<T>(T(0), T(0));
+                            qnext = mk<T>(qp.x - w.x * qnext.x, qp.y - w.y * qnext.y);
+                        }
+                        un = mk<T>(nxt.x - corr.x * qnext.x, nxt.y - corr.y * qnext.y);
+                    }
+                    work[l * kSLdy + pad(e)] = un;
+                    if (sing && e == 0) csum += (double)un.x;
                 }
             }
             st = nxt;
@@ -528,7 +608,8 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
 
 template <typename T, bool FULL>
 static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    hipLaunchKernelGGL((k_zpipe<T, FULL>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
+    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, FULL, true>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
+    else hipLaunchKernelGGL((k_zpipe<T, FULL, false>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
     return hipGetLastError();
 }
 

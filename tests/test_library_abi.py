@@ -49,7 +49,10 @@ def _create(lib, nx, ny, nz, bc, h=(1.0, 1.0, 1.0), dtype=0, batch=1):
     ((6, 9, 5, "NNPPDN"), 0),
     ((8, 8, 8, "PDPPDD"), -2),     # mixed x faces
     ((8, 8, 8, "PPNDDD"), -2),     # mixed y faces
-    ((8, 8, 8, "PPPPPP"), -2),     # periodic z not supported
+    ((8, 8, 8, "PPPPPP"), 0),      # periodic z (Sherman-Morrison)
+    ((8, 8, 3, "DDNNPP"), 0),
+    ((8, 8, 2, "PPPPPP"), -3),     # periodic z needs nz >= 3
+    ((8, 8, 8, "PPPPPD"), -2),     # one periodic z face
     ((8, 8, 8, "PPPPXD"), -2),     # unknown face type
     ((10, 8, 8, "PPPPDD"), -3),    # prime factor 5
     ((8, 14, 8, "PPPPDD"), -3),    # prime factor 7
