@@ -73,11 +73,12 @@ def traffic_for(group, workload, dtype):
     return None if entry is None else entry.get("bytes_per_launch")
 
 
-def time_solves(plan, f, u, steps, warmup, lib):
+def time_solves(plan, f, u, steps, warmup, lib, faces=None):
     import ctypes
     import torch
+    kw = {} if faces is None else {"faces": faces}
     for _ in range(warmup):
-        plan.solve(f, u)
+        plan.solve(f, u, **kw)
     torch.cuda.synchronize()
     lib.pp_plan_set_timing(plan._handle, 1)
     lib.pp_plan_kernel_times(plan._handle, None, None, 1)
@@ -87,7 +88,7 @@ def time_solves(plan, f, u, steps, warmup, lib):
     t0 = time.perf_counter()
     start.record()
     for _ in range(steps):
-        plan.solve(f, u)
+        plan.solve(f, u, **kw)
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -174,6 +175,8 @@ def main():
     ap.add_argument("--workload", default="div_ppn")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-refined", action="store_true")
+    ap.add_argument("--skip-faces", action="store_true", help="skip timing the solve with face values")
+    ap.add_argument("--skip-periodic-z", action="store_true", help="skip timing the periodic-z solve")
     ap.add_argument("--skip-check", action="store_true", help="skip the host-side backward-error check")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) three times, as the reference "
@@ -256,6 +259,39 @@ def main():
         eta = max(oracle.backward_error(fp[b], u64[b], bc, h) for b in range(batch))
         result["f64_backward_error"] = float(eta)
         log(f"f64 backward error {eta:.2e}")
+
+    if not args.skip_faces:
+        # the same solve with non-homogeneous data on every non-periodic face
+        # (Dirichlet values / Neumann fluxes drawn N(0,1), seeded), through pp_solve_bc
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        faces = []
+        for i in range(6):
+            if bc[i] == "P":
+                faces.append(None)
+                continue
+            faces.append(torch.randn(plan.face_shape(i), generator=gen, device="cuda", dtype=torch.float64))
+        uf = torch.empty_like(f)
+        ms_fc, _, per_fc = time_solves(plan, f, uf, args.steps, args.warmup, lib, faces=faces)
+        result["faces"] = {
+            "value": round(npts / ms_fc / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_fc, 4),
+            "faces": [bc[i] for i in range(6) if faces[i] is not None],
+            "kernels": {g: dict(per_fc[g]) for g in GROUPS},
+        }
+        log(f"f64 with face values: {ms_fc:.3f} ms/solve")
+        del faces, uf
+
+    if not args.skip_periodic_z and bc[4:6] != "PP":
+        # the same source with the z faces made periodic (cyclic z-systems)
+        bcp = bc[:4] + "PP"
+        plan_p = Plan(shape, bcp, h, dtype="f64", batch=batch)
+        up = torch.empty_like(f)
+        ms_p, _, per_p = time_solves(plan_p, f, up, args.steps, args.warmup, lib)
+        result["periodic_z"] = {
+            "bc": bcp, "value": round(npts / ms_p / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_p, 4),
+            "kernels": {g: dict(per_p[g]) for g in GROUPS},
+        }
+        log(f"f64 with periodic z ({bcp}): {ms_p:.3f} ms/solve")
+        del plan_p, up
 
     if not args.skip_refined:
         plan_r = Plan(shape, bc, h, dtype="f32_refined", batch=batch)

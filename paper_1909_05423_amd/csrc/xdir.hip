@@ -196,25 +196,15 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
             const int p = FULL ? 0 : fdiv(r, inv_epl);
             const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
             if (FULL || (j < nlines && n < nx)) {
-                double la = 0.0, lb = 0.0;   // lift of rows ya, ya + 1 at column n
-                if constexpr (FACES) {
-                    const int ya = xb.y0 + 2 * j;
-                    if constexpr (FULL) {
-                        if (n == 0) {
-                            la += fa.c[0] * (double)gx[0];
-                            lb += fa.c[0] * (double)gx[1];
-                        }
-                        if (n == nx - 1) {
-                            la += fa.c[1] * (double)gx[2];
-                            lb += fa.c[1] * (double)gx[3];
-                        }
-                        if (ya == 0 || ya + 1 == ny - 1 || xb.z == 0 || xb.z == nz - 1) {
-                            la += face_lift_yz(fa, xb.b, n, ya, xb.z, nx, ny, nz);
-                            lb += face_lift_yz(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
-                        }
-                    } else {
-                        if (ya < ny) la = face_lift(fa, xb.b, n, ya, xb.z, nx, ny, nz);
-                        if (ya + 1 < ny) lb = face_lift(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
+                double la = 0.0, lb = 0.0;   // x-face lift of rows ya, ya + 1 at column n (FULL)
+                if constexpr (FACES && FULL) {
+                    if (n == 0) {
+                        la += fa.c[0] * (double)gx[0];
+                        lb += fa.c[0] * (double)gx[1];
+                    }
+                    if (n == nx - 1) {
+                        la += fa.c[1] * (double)gx[2];
+                        lb += fa.c[1] * (double)gx[3];
                     }
                 }
                 const double fa_ = (double)ra[r] - la, fb_ = (double)rb[r] - lb;
@@ -230,6 +220,39 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                     }
                 }
                 lds[j * ldl + pad(pos)] = mk<T>(va, vb);
+            }
+        }
+        // the remaining face lifts, applied to the lines in place: y and z faces
+        // (boundary rows and planes only; FULL) or every face (general form)
+        if constexpr (FACES) {
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                const int p = FULL ? 0 : fdiv(r, inv_epl);
+                const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
+                const int ya = xb.y0 + 2 * j;
+                const bool edge = FULL ? (ya == 0 || ya + 1 == ny - 1 || xb.z == 0 || xb.z == nz - 1)
+                                       : (j < nlines && n < nx);
+                if (edge) {
+                    double la = 0.0, lb = 0.0;
+                    if constexpr (FULL) {
+                        la = face_lift_yz(fa, xb.b, n, ya, xb.z, nx, ny, nz);
+                        lb = face_lift_yz(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
+                    } else {
+                        if (ya < ny) la = face_lift(fa, xb.b, n, ya, xb.z, nx, ny, nz);
+                        if (ya + 1 < ny) lb = face_lift(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
+                    }
+                    int pos = n;
+                    double sg = 1.0;
+                    if (a.bx != BC_P) {
+                        pos = makhoul_pos(n, nx);
+                        if (a.bx == BC_D && (n & 1)) sg = -1.0;
+                    }
+                    cplx<T>& v = lds[j * ldl + pad(pos)];
+                    const double fa_ = sg * (double)v.x - la, fb_ = sg * (double)v.y - lb;
+                    acc -= la + lb;
+                    amax = fmax(amax, fmax(fabs(fa_), fabs(fb_)));
+                    v = mk<T>((T)(sg * fa_), (T)(sg * fb_));
+                }
             }
         }
         // the next block's rows (past the end: this block's again, unused)
