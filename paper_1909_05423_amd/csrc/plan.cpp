@@ -44,6 +44,8 @@ struct pp_plan_s {
     // tables (uploaded into the workspace)
     std::vector<unsigned char> blob;
     size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
+    size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
+    int zsolver = 0;     // 0 Thomas (fused march), 1 PCR
     // periodic z (Sherman-Morrison)
     size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
            t_invgam = 0;
@@ -356,6 +358,29 @@ template <typename T> void build_tables(pp_plan p) {
             }
         }
     }
+    // interior diagonal hz^2 lam - 2 of every z-system (PCR); padding parts get a
+    // harmless non-singular value (their right-hand side is zero)
+    {
+        p->t_bmid = em.put(sizeof(T) * 2 * (size_t)slots * ny);
+        T* bm = reinterpret_cast<T*>(p->blob.data() + p->t_bmid);
+        const double hz2 = p->h[2] * p->h[2];
+        for (int m = 0; m < slots; ++m) {
+            const bool pairslot = (p->bx != pp::BC_P) || (m == 0);
+            const bool sep = (p->by == pp::BC_P) && pairslot;
+            for (int e = 0; e < ny; ++e)
+                for (int part = 0; part < 2; ++part) {
+                    int kx, ky;
+                    if (sep && e != 0 && 2 * e != ny) {
+                        kx = kx_of(m, e < ny - e ? 0 : 1);
+                        ky = e;
+                    } else {
+                        kx = kx_of(m, part);
+                        ky = (p->by == pp::BC_D) ? ny - 1 - e : e;
+                    }
+                    bm[((size_t)m * ny + e) * 2 + part] = (kx < 0) ? T(-3) : (T)(-2.0 + hz2 * (lamx[kx] + lamy[ky]));
+                }
+        }
+    }
     if (p->bz0 != pp::BC_P) return;
     // periodic z: Sherman-Morrison rows (alpha, qp) per slot, and per-entry scalars
     auto emit_rows = [&](std::vector<T> Line<T>::*vec, size_t* t_off, size_t* t_len, size_t* t_rows) {
@@ -464,6 +489,10 @@ template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, 
     a.wrows = reinterpret_cast<const cplx<T>*>(t + p->t_wrows);
     a.winf = reinterpret_cast<const cplx<T>*>(t + p->t_winf);
     a.wlast = reinterpret_cast<const cplx<T>*>(t + p->t_wlast);
+    a.zsolver = p->zsolver;
+    a.bz0 = p->bz0;
+    a.bz1 = p->bz1;
+    a.bmid = reinterpret_cast<const cplx<T>*>(t + p->t_bmid);
     a.zper = (p->bz0 == pp::BC_P) ? 1 : 0;
     if (a.zper) {
         a.aoff = reinterpret_cast<const int*>(t + p->t_aoff);
@@ -825,6 +854,16 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge) {
     if (!p) return PP_ERR_ARG;
     if (gauge != PP_GAUGE_MEAN && gauge != PP_GAUGE_PIN && gauge != PP_GAUGE_PIN_RAW) return PP_ERR_ARG;
     p->gauge = gauge;
+    return PP_OK;
+}
+
+pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver) {
+    if (!p || (solver != PP_ZSOLVER_THOMAS && solver != PP_ZSOLVER_PCR)) return PP_ERR_ARG;
+    if (solver == PP_ZSOLVER_PCR) {
+        if (p->bz0 == pp::BC_P) return PP_ERR_BC;
+        if (p->nz > 512 || p->ny > 512) return PP_ERR_SIZE;
+    }
+    p->zsolver = (int)solver;
     return PP_OK;
 }
 

@@ -116,6 +116,10 @@ template <typename T> struct MidArgs {
     int zper;
     const int *aoff, *alen, *qoff, *qlen;
     const cplx<T> *arows, *qrows, *qlast, *inv_den, *inv_gamma;
+    // z solver: 0 = fused Thomas march, 1 = parallel cyclic reduction (separate y passes)
+    int zsolver;
+    int bz0, bz1;            // z face types (Bc) of the end rows
+    const cplx<T>* bmid;     // [slot][ny] interior diagonal hz^2 lam - 2 of each part's z-system
     const double* mu;        // [batch] source means
     double* cmean;           // [batch] mean of the zero-mode solution line (output)
 };
@@ -157,6 +161,11 @@ hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float
 
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);
+
+// The same stage with the z-systems solved by parallel cyclic reduction
+// (y transforms as separate passes; nz <= 512, ny <= 512, z not periodic).
+template <typename T>
+hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);
 
 // Finalise the x-forward partials: mu[b] = sum / npts, scalars[SC_MAXF] = max |f|.
 hipError_t launch_finalize_xfwd(const double* partial, int nper, int batch, double npts, double* mu,

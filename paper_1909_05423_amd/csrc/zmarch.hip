@@ -630,6 +630,7 @@ static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, h
 // two z entries per thread (ny <= 1024) or 32 and 4 (ny <= 2048).
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+    if (a.zsolver == 1) return launch_mid_pcr<T>(S, a, batch, s);
     if (a.ny <= kSNy) {
         if (a.ny == kSNy && a.nz % kSZ == 0) return launch_pipe<T, true>(S, a, batch, s);
         return launch_pipe<T, false>(S, a, batch, s);

@@ -1,0 +1,275 @@
+// Alternative z solver: parallel cyclic reduction (section "Parallel Cyclic
+// Reduction").  Selected per plan; the default is the fused Thomas march.
+//
+// PCR needs a whole z line of a mode on chip at once, while the y transform
+// needs a whole y line of a plane, so this path runs them as separate passes
+// over the spectral array S:
+//   k_ypass<FWD>   y transform of every (slot, plane), in place;
+//   k_zpcr         PCR along z for tiles of TE entries of one slot, the whole
+//                  line of each entry in LDS;
+//   k_ypass<INV>   inverse y transform, in place.
+// Two more HBM sweeps than the fused march (the point of the comparison).
+//
+// PCR on the normalised system (diagonal 1): row j reads
+//     a_j u_{j-1} + u_j + c_j u_{j+1} = x_j,
+// and one level with stride s replaces it by a combination of rows j-s, j, j+s:
+//     r = 1 / (1 - a_j c_{j-s} - c_j a_{j+s})
+//     a_j <- -r a_j a_{j-s},  c_j <- -r c_j c_{j+s},
+//     x_j <- r (x_j - a_j x_{j-s} - c_j x_{j+s}),
+// with rows outside [0, n) taken as zero.  After ceil(log2 n) levels every row
+// is decoupled and x_j = u_j.  Every row of a level reads the old values of
+// its neighbours: the level reads into registers, then writes back after a
+// barrier.  The zero mode of a singular problem is pinned (row 0: u_0 = 0).
+
+#include "pp_kernels.hpp"
+
+namespace pp {
+
+// ---------------------------------------------------------------- y passes
+// One 512-thread workgroup per (slot, 8 planes, batch entry); one plane per
+// wavefront, transformed in a padded LDS line with the wavefront-private FFT.
+template <typename T, bool INV>
+__global__ __launch_bounds__(512) void k_ypass(cplx<T>* __restrict__ S, MidArgs<T> a) {
+    constexpr int LDY = 576;
+    __shared__ __align__(16) cplx<T> work[8 * LDY];
+    __shared__ __align__(16) cplx<T> twl[512];
+    __shared__ __align__(16) cplx<T> mkl[512];
+    const int m = blockIdx.x, b = blockIdx.z;
+    const int ny = a.ny, nz = a.nz;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int i = tid; i < ny; i += 512) {
+        twl[i] = a.twy[i];
+        mkl[i] = a.mky[i];
+    }
+    __syncthreads();
+    const int z = blockIdx.y * 8 + wave;
+    if (z >= nz) return;
+    const bool pairslot = (a.bx != BC_P) || (m == 0);
+    const bool sep = (a.by == BC_P) && pairslot;
+    const int half = (ny >> 1) + 1;
+    cplx<T>* plane = S + (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride + (size_t)z * a.zstride;
+    cplx<T>* line = work + wave * LDY;
+    if (!INV) {
+        for (int y = lane; y < ny; y += 64) {
+            cplx<T> v = plane[y];
+            int pos = y;
+            if (a.by != BC_P) {
+                pos = makhoul_pos(y, ny);
+                if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+            }
+            line[pad(pos)] = v;
+        }
+        wave_lds_sync();
+        wfft<8, false, T>(line, a.fy, twl, lane);
+        if (a.by != BC_P) {
+            for (int k = lane; k < half; k += 64) {
+                if (k == 0) continue;
+                const cplx<T> vk = line[pad(k)];
+                const cplx<T> wk = mkl[k];
+                if (2 * k == ny) {
+                    line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vk, wk)), T(0.5));
+                } else {
+                    const cplx<T> vr = line[pad(ny - k)];
+                    const cplx<T> wr = mkl[ny - k];
+                    line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), T(0.5));
+                    line[pad(ny - k)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), T(0.5));
+                }
+            }
+        } else if (sep) {
+            for (int k = lane; k < half; k += 64) {
+                if (k == 0 || 2 * k >= ny) continue;
+                const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
+                line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+            }
+        }
+        wave_lds_sync();
+        for (int e = lane; e < ny; e += 64) plane[e] = line[pad(e)];
+    } else {
+        for (int e = lane; e < ny; e += 64) line[pad(e)] = plane[e];
+        wave_lds_sync();
+        if (a.by != BC_P) {
+            for (int k = lane; k < half; k += 64) {
+                if (k == 0) continue;
+                const cplx<T> xk = line[pad(k)];
+                if (2 * k == ny) {
+                    line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), mkl[k]);
+                } else {
+                    const cplx<T> xr = line[pad(ny - k)];
+                    line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), mkl[k]);
+                    line[pad(ny - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), mkl[ny - k]);
+                }
+            }
+        } else if (sep) {
+            for (int k = lane; k < half; k += 64) {
+                if (k == 0 || 2 * k >= ny) continue;
+                const cplx<T> A = line[pad(k)], B = line[pad(ny - k)];
+                line[pad(k)] = mk<T>(A.x - B.y, A.y + B.x);
+                line[pad(ny - k)] = mk<T>(A.x + B.y, B.x - A.y);
+            }
+        }
+        wave_lds_sync();
+        wfft<8, true, T>(line, a.fy, twl, lane);
+        for (int y = lane; y < ny; y += 64) {
+            int pos = y;
+            if (a.by != BC_P) pos = makhoul_pos(y, ny);
+            cplx<T> v = line[pad(pos)];
+            if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+            plane[y] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- PCR along z
+// TE entries of one slot per 256-thread workgroup; LDS holds, per (entry, z),
+// the right-hand side x (complex: the real and imaginary parts are separate
+// systems) and the two off-diagonals of each part.  The reduction runs in
+// double for either solve precision: its log2(nz) levels of combined rows lose
+// more to rounding than the Thomas recurrence does, which in float exceeds the
+// unrefined float tolerance on long lines.
+constexpr int kPcrThreads = 256;
+template <typename T> constexpr int pcr_te() { return 4; }
+template <typename T> constexpr size_t pcr_lds_bytes(int nz) {
+    return (size_t)pcr_te<T>() * nz * (sizeof(double2) + 4 * sizeof(double)) + 64 * sizeof(double);
+}
+
+template <typename Tio>
+__global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a) {
+    using T = double;
+    constexpr int TE = pcr_te<Tio>();
+    constexpr int ITEMS = 512 * TE / kPcrThreads;   // (entry, z) rows per thread at nz = 512
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nz = a.nz, ny = a.ny;
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int e0 = blockIdx.x * TE;
+    const int tid = threadIdx.x;
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(smem);            // [z][TE]
+    T* AC = reinterpret_cast<T*>(X + (size_t)nz * TE);         // [z][TE][4]: a.x, a.y, c.x, c.y
+    double* red = reinterpret_cast<double*>(AC + (size_t)nz * TE * 4);
+    const size_t base = (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride;
+    const bool sing = a.singular && m == 0;
+    const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
+    const T d0 = (a.bz0 == BC_D) ? T(-1) : T(1), d1 = (a.bz1 == BC_D) ? T(-1) : T(1);
+    const int nrows = nz * TE;
+    // load, scale and normalise (rows of the tile: r = z * TE + el)
+    for (int r = tid; r < nrows; r += kPcrThreads) {
+        const int z = r / TE, el = r - z * TE, e = e0 + el;
+        cplx<T> x = mk<T>(T(0), T(0));
+        cplx<T> bm = mk<T>(T(1), T(1));
+        if (e < ny) {
+            const cplx<Tio> xs = S[base + (size_t)z * a.zstride + e];
+            const cplx<Tio> bs = a.bmid[(size_t)m * ny + e];
+            x = mk<T>((T)xs.x * (T)a.scale, (T)xs.y * (T)a.scale);
+            bm = mk<T>((T)bs.x, (T)bs.y);
+        }
+        const bool pin = sing && e == 0;   // part x of the zero mode: row 0 reads u_0 = 0
+        if (pin) x.x -= proj;
+        cplx<T> bd = bm;
+        if (z == 0) bd = mk<T>(bd.x + d0, bd.y + d0);
+        if (z == nz - 1) bd = mk<T>(bd.x + d1, bd.y + d1);
+        if (nz == 1) bd = mk<T>(bm.x + d0 + d1, bm.y + d0 + d1);
+        const cplx<T> ib = mk<T>(T(1) / bd.x, T(1) / bd.y);
+        T ax = (z > 0) ? ib.x : T(0), ay = (z > 0) ? ib.y : T(0);
+        T cx = (z < nz - 1) ? ib.x : T(0), cy = (z < nz - 1) ? ib.y : T(0);
+        T xx = x.x * ib.x, xy = x.y * ib.y;
+        if (pin && z == 0) {
+            ax = cx = T(0);
+            xx = T(0);
+        }
+        if (pin && z == 1) ax = T(0);   // coupling to the pinned u_0 = 0
+        X[r] = mk<T>(xx, xy);
+        T* ac = AC + (size_t)r * 4;
+        ac[0] = ax;
+        ac[1] = ay;
+        ac[2] = cx;
+        ac[3] = cy;
+    }
+    __syncthreads();
+    for (int s = 1; s < nz; s <<= 1) {
+        cplx<T> nx_[ITEMS];
+        T na[ITEMS][4];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int r = tid + k * kPcrThreads;
+            if (r >= nrows) continue;
+            const int z = r / TE;
+            const T* ac = AC + (size_t)r * 4;
+            const cplx<T> x = X[r];
+            T am[4] = {T(0), T(0), T(0), T(0)}, ap[4] = {T(0), T(0), T(0), T(0)};
+            cplx<T> xm = mk<T>(T(0), T(0)), xp = xm;
+            if (z - s >= 0) {
+                const T* q = AC + (size_t)(r - s * TE) * 4;
+                am[0] = q[0];
+                am[1] = q[1];
+                am[2] = q[2];
+                am[3] = q[3];
+                xm = X[r - s * TE];
+            }
+            if (z + s < nz) {
+                const T* q = AC + (size_t)(r + s * TE) * 4;
+                ap[0] = q[0];
+                ap[1] = q[1];
+                ap[2] = q[2];
+                ap[3] = q[3];
+                xp = X[r + s * TE];
+            }
+            // part x: a = ac[0], c = ac[2]; part y: a = ac[1], c = ac[3]
+            const T rx = T(1) / (T(1) - ac[0] * am[2] - ac[2] * ap[0]);
+            const T ry = T(1) / (T(1) - ac[1] * am[3] - ac[3] * ap[1]);
+            na[k][0] = -rx * ac[0] * am[0];
+            na[k][1] = -ry * ac[1] * am[1];
+            na[k][2] = -rx * ac[2] * ap[2];
+            na[k][3] = -ry * ac[3] * ap[3];
+            nx_[k] = mk<T>(rx * (x.x - ac[0] * xm.x - ac[2] * xp.x), ry * (x.y - ac[1] * xm.y - ac[3] * xp.y));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int r = tid + k * kPcrThreads;
+            if (r >= nrows) continue;
+            T* ac = AC + (size_t)r * 4;
+            ac[0] = na[k][0];
+            ac[1] = na[k][1];
+            ac[2] = na[k][2];
+            ac[3] = na[k][3];
+            X[r] = nx_[k];
+        }
+        __syncthreads();
+    }
+    // store; the mean of the zero-mode line for the zero-mean gauge
+    double csum = 0.0;
+    for (int r = tid; r < nrows; r += kPcrThreads) {
+        const int z = r / TE, el = r - z * TE, e = e0 + el;
+        if (e >= ny) continue;
+        const cplx<T> u = X[r];
+        S[base + (size_t)z * a.zstride + e] = mk<Tio>((Tio)u.x, (Tio)u.y);
+        if (sing && e == 0) csum += (double)u.x;
+    }
+    if (m == 0 && blockIdx.x == 0) {
+        const double tot = block_sum<kPcrThreads>(csum, red);
+        if (tid == 0) a.cmean[b] = (sing && a.demean) ? tot / (double)nz : 0.0;
+    }
+}
+
+template <typename T>
+hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+    const dim3 gy(a.slots, (a.nz + 7) / 8, batch);
+    hipLaunchKernelGGL((k_ypass<T, false>), gy, dim3(512), 0, s, S, a);
+    const size_t lds = pcr_lds_bytes<T>(a.nz);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zpcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)pcr_lds_bytes<T>(512));
+        attr = true;
+    }
+    const dim3 gz((a.ny + pcr_te<T>() - 1) / pcr_te<T>(), a.slots, batch);
+    hipLaunchKernelGGL((k_zpcr<T>), gz, dim3(kPcrThreads), lds, s, S, a);
+    hipLaunchKernelGGL((k_ypass<T, true>), gy, dim3(512), 0, s, S, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_mid_pcr<double>(cplx<double>*, const MidArgs<double>&, int, hipStream_t);
+template hipError_t launch_mid_pcr<float>(cplx<float>*, const MidArgs<float>&, int, hipStream_t);
+
+}  // namespace pp

@@ -16,6 +16,7 @@ from . import _lib
 DTYPES = {"f64": (_lib.PP_F64, torch.float64), "f32": (_lib.PP_F32, torch.float32),
           "f32_refined": (_lib.PP_F32_REFINED, torch.float64)}
 GAUGES = {"mean": _lib.PP_GAUGE_MEAN, "pin": _lib.PP_GAUGE_PIN, "pin_raw": _lib.PP_GAUGE_PIN_RAW}
+ZSOLVERS = {"thomas": 0, "pcr": 1}
 
 
 class Plan:
@@ -23,7 +24,7 @@ class Plan:
     (x-, x+, y-, y+, z-, z+ from 'P', 'D', 'N') and spacings h = (hx, hy, hz)."""
 
     def __init__(self, shape, bc, h, dtype="f64", batch=1, gauge="mean", device=None,
-                 refine_tol=None, refine_max_iter=None):
+                 refine_tol=None, refine_max_iter=None, zsolver="thomas"):
         lib = _lib.load()
         nz, ny, nx = (int(v) for v in shape)
         if dtype not in DTYPES:
@@ -45,6 +46,10 @@ class Plan:
                    "pp_plan_create")
         self._handle = handle
         _lib.check(lib.pp_plan_set_gauge(handle, GAUGES[gauge]), "pp_plan_set_gauge")
+        if zsolver not in ZSOLVERS:
+            raise ValueError(f"zsolver must be one of {sorted(ZSOLVERS)}")
+        _lib.check(lib.pp_plan_set_zsolver(handle, ZSOLVERS[zsolver]), "pp_plan_set_zsolver")
+        self.zsolver = zsolver
         if refine_tol is not None or refine_max_iter is not None:
             _lib.check(lib.pp_plan_set_refinement(handle, 1e-13 if refine_tol is None else float(refine_tol),
                                                   8 if refine_max_iter is None else int(refine_max_iter)),

@@ -1,0 +1,84 @@
+"""GPU parity of the alternative z solver (parallel cyclic reduction, y
+transforms as separate passes) against the oracle, whose z solve is the
+general Thomas algorithm pinned to dense LU; and at full size against the
+backward-error bar.  Tolerances as for the default solver.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+BCS = [x * 2 + y * 2 + z for x in "PND" for y in "PND" for z in ("DD", "NN", "DN", "ND")]
+SHAPES = [(7, 12, 16), (5, 9, 6), (3, 1, 4), (1, 4, 3), (2, 3, 1), (37, 36, 48), (20, 32, 27), (64, 8, 8)]
+
+
+def _solve(f, bc, h, dtype="f64", gauge="mean", adjoint=False):
+    import torch
+    from paper_1909_05423_amd import Plan
+    from gpu_util import to_dev
+    f = np.asarray(f)
+    plan = Plan(f.shape, bc, h, dtype=dtype, gauge=gauge, zsolver="pcr")
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    fd = to_dev(f.reshape((1,) + f.shape), tdt)
+    u = plan.adjoint(fd) if adjoint else plan.solve(fd)
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy().reshape(f.shape), plan
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_pcr_f64_all_bcs(bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(97 + sum(map(ord, bc)))
+    for shape in SHAPES:
+        banner(f"pcr f64 {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal(shape)
+        u, _ = _solve(f, bc, h)
+        assert rel_max(u, oracle.solve(f, bc, h, "mean")) < 1e-12, (bc, shape)
+
+
+@pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDN", "NNDDND", "PPPPDD"])
+def test_pcr_f32_refined_gauges_adjoint(bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(101 + sum(map(ord, bc)))
+    for shape in [(8, 12, 16), (37, 36, 48)]:
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal(shape) + 0.2
+        banner(f"pcr refined {bc} {shape}")
+        u, _ = _solve(f, bc, h, dtype="f32_refined")
+        assert rel_max(u, oracle.solve(f, bc, h, "mean")) < 1e-12
+        f32 = f.astype(np.float32).astype(np.float64)
+        banner(f"pcr f32 {bc} {shape}")
+        u, _ = _solve(f32, bc, h, dtype="f32")
+        assert rel_max(u, oracle.solve(f32, bc, h, "mean")) < 1e-5
+        for gauge in ["pin", "pin_raw"]:
+            banner(f"pcr {gauge} {bc} {shape}")
+            u, _ = _solve(f, bc, h, gauge=gauge)
+            assert rel_max(u, oracle.solve(f, bc, h, gauge)) < 1e-12
+        banner(f"pcr adjoint {bc} {shape}")
+        v, _ = _solve(f, bc, h, adjoint=True)
+        assert rel_max(v, oracle.solve_adjoint(f, bc, h, "mean")) < 1e-12
+
+
+def test_pcr_full_size_backward_error_and_agreement():
+    """512^3 divergence workload: the PCR solve meets the backward-error bar and
+    agrees with the default (Thomas) solve."""
+    import torch
+    import workloads
+    from paper_1909_05423_amd import Plan
+    from gpu_util import banner
+    wl = workloads.make("div_ppn")
+    f = torch.from_numpy(wl["f"]).cuda()
+    banner("pcr 512^3 div_ppn")
+    up = Plan(wl["shape"], wl["bc"], wl["h"], zsolver="pcr").solve(f)
+    ut = Plan(wl["shape"], wl["bc"], wl["h"]).solve(f)
+    torch.cuda.synchronize()
+    diff = float((up - ut).abs().max() / ut.abs().max())
+    assert diff < 1e-12, diff
+    u = up.cpu().numpy()[0]
+    fh = wl["f"][0] - wl["f"][0].mean()
+    eta = oracle.backward_error(fh, u, wl["bc"], wl["h"])
+    assert eta < 1e-14, eta

@@ -130,3 +130,22 @@ def test_face_argument_errors_before_any_gpu_call(lib):
     faces[2] = 0x400000 + 256                                                # inside the workspace
     assert lib.pp_solve_bc(p, f, faces, u, ws, None) == -4
     lib.pp_plan_destroy(p)
+
+
+def test_zsolver_option(lib):
+    st, p = _create(lib, 8, 8, 8, "PPPPDD")
+    assert st == 0
+    assert lib.pp_plan_set_zsolver(p, 1) == 0
+    assert lib.pp_plan_set_zsolver(p, 0) == 0
+    assert lib.pp_plan_set_zsolver(p, 2) == -1
+    lib.pp_plan_destroy(p)
+    st, p = _create(lib, 8, 8, 8, "PPPPPP")
+    assert st == 0 and lib.pp_plan_set_zsolver(p, 1) == -2     # periodic z: Thomas only
+    lib.pp_plan_destroy(p)
+    st, p = _create(lib, 8, 8, 1024, "PPPPDD")
+    assert st == 0 and lib.pp_plan_set_zsolver(p, 1) == -3     # z lines longer than 512
+    lib.pp_plan_destroy(p)
+    st, p = _create(lib, 8, 1024, 8, "PPPPDD")
+    assert st == 0 and lib.pp_plan_set_zsolver(p, 1) == -3     # y lines longer than 512
+    lib.pp_plan_destroy(p)
+
