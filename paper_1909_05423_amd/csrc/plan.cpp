@@ -265,12 +265,24 @@ template <typename T> void build_tables(pp_plan p) {
     p->blob.clear();
     Emit<T> em{p->blob};
     const int nx = p->nx, ny = p->ny, nz = p->nz;
-    auto twiddles = [&](int n, size_t* tw, size_t* mkt) {
+    // FFT twiddles packed by stage (the layout the wavefront FFT reads): the
+    // stage with sub-transform length Ls and radix R holds exp(-2 pi i t k step / n),
+    // step = n / (Ls R), at index t Ls + k - 1 (t = 1..R-1, k = 0..Ls-1)
+    auto twiddles = [&](const pp::FftDesc& fd, size_t* tw, size_t* mkt) {
+        const int n = fd.n;
         *tw = em.put(sizeof(cplx<T>) * n);
-        for (int j = 0; j < n; ++j) {
-            double c, s;
-            cos_sin_pi(2LL * j, n, &c, &s);  // exp(-2 pi i j / n)
-            em.cp(*tw)[j] = pp::mk<T>((T)c, (T)-s);
+        em.cp(*tw)[n - 1] = pp::mk<T>(T(1), T(0));   // unused
+        long long Ls = 1;
+        for (int st = 0; st < fd.nstages; ++st) {
+            const int R = fd.radix[st];
+            const long long step = n / (Ls * R);
+            for (int t = 1; t < R; ++t)
+                for (long long k = 0; k < Ls; ++k) {
+                    double c, s;
+                    cos_sin_pi(2LL * t * k * step, n, &c, &s);
+                    em.cp(*tw)[t * Ls + k - 1] = pp::mk<T>((T)c, (T)-s);
+                }
+            Ls *= R;
         }
         *mkt = em.put(sizeof(cplx<T>) * n);
         for (int k = 0; k < n; ++k) {
@@ -279,8 +291,8 @@ template <typename T> void build_tables(pp_plan p) {
             em.cp(*mkt)[k] = pp::mk<T>((T)c, (T)-s);
         }
     };
-    twiddles(nx, &p->t_twx, &p->t_mkx);
-    twiddles(ny, &p->t_twy, &p->t_mky);
+    twiddles(p->fx, &p->t_twx, &p->t_mkx);
+    twiddles(p->fy, &p->t_twy, &p->t_mky);
 
     std::vector<double> lamx(nx), lamy(ny);
     for (int k = 0; k < nx; ++k) lamx[k] = eigenvalue(p->bx, k, nx, p->h[0]);

@@ -155,123 +155,6 @@ struct FftDesc {
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// One Stockham stage over `nlines` lines.  Every butterfly of the stage is
-// held in registers between the two barriers, so the update is in place.
-// MAXB bounds the butterflies one thread owns: nlines*N/R <= MAXB*NTH.
-template <int R, int MAXB, int NTH, bool INV, typename T>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int ldl, int nlines, int N, int Ls,
-                                          const cplx<T>* __restrict__ tw) {
-    const int nbf = N / R;
-    const int total = nlines * nbf;
-    const int step = N / (Ls * R);
-    const int tid = threadIdx.x;
-    const float inv_nbf = 1.0f / (float)nbf, inv_ls = 1.0f / (float)Ls;
-    cplx<T> v[MAXB][R];
-    int dline[MAXB], didx[MAXB];
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        const int bidx = tid + i * NTH;
-        dline[i] = -1;
-        if (bidx < total) {
-            const int line = fdiv(bidx, inv_nbf);
-            const int j = bidx - line * nbf;
-            const int k = j - fdiv(j, inv_ls) * Ls;
-            const cplx<T>* src = buf + line * ldl;
-#pragma unroll
-            for (int t = 0; t < R; ++t) v[i][t] = src[pad(j + t * nbf)];
-            if (Ls > 1) {
-#pragma unroll
-                for (int t = 1; t < R; ++t) {
-                    const cplx<T> w = tw[t * k * step];
-                    v[i][t] = INV ? cmulc(v[i][t], w) : cmul(v[i][t], w);
-                }
-            }
-            bfly<R, INV, T>(v[i]);
-            dline[i] = line * ldl;
-            didx[i] = (j - k) * R + k;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-        if (dline[i] >= 0) {
-#pragma unroll
-            for (int t = 0; t < R; ++t) buf[dline[i] + pad(didx[i] + t * Ls)] = v[i][t];
-        }
-    }
-    __syncthreads();
-}
-
-// Transform `nlines` lines of d.n complex values in LDS, in place, with NTH
-// threads owning at most EPT values each (nlines * d.n <= NTH * EPT).  Callers
-// synchronise before the call; the call ends with a barrier.
-template <int NTH, int EPT, bool INV, typename T>
-__device__ void fft_lines(cplx<T>* buf, int ldl, int nlines, const FftDesc& d, const cplx<T>* __restrict__ tw) {
-    int Ls = 1;
-    for (int s = 0; s < d.nstages; ++s) {
-        const int R = d.radix[s];
-        if (R == 8) fft_stage<8, cdiv(EPT, 8), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        else if (R == 4) fft_stage<4, cdiv(EPT, 4), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        else if (R == 3) fft_stage<3, cdiv(EPT, 3), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        else fft_stage<2, cdiv(EPT, 2), NTH, INV, T>(buf, ldl, nlines, d.n, Ls, tw);
-        Ls *= R;
-    }
-}
-
-// Ping-pong variant of a Stockham stage: reads `src`, writes `dst`, one
-// barrier; each butterfly goes straight from its loads to its stores, so only
-// one butterfly is live per thread at a time.
-template <int R, int NTH, bool INV, typename T>
-__device__ __forceinline__ void fft_stage_pp(const cplx<T>* src, cplx<T>* dst, int ldl, int nlines, int N, int Ls,
-                                             const cplx<T>* tw) {
-    const int nbf = N / R;
-    const int total = nlines * nbf;
-    const int step = N / (Ls * R);
-    const float inv_nbf = 1.0f / (float)nbf, inv_ls = 1.0f / (float)Ls;
-    for (int bidx = threadIdx.x; bidx < total; bidx += NTH) {
-        const int line = fdiv(bidx, inv_nbf);
-        const int j = bidx - line * nbf;
-        const int k = j - fdiv(j, inv_ls) * Ls;
-        const cplx<T>* s = src + line * ldl;
-        cplx<T> v[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = s[pad(j + t * nbf)];
-        if (Ls > 1) {
-#pragma unroll
-            for (int t = 1; t < R; ++t) {
-                const cplx<T> w = tw[t * k * step];
-                v[t] = INV ? cmulc(v[t], w) : cmul(v[t], w);
-            }
-        }
-        bfly<R, INV, T>(v);
-        cplx<T>* d = dst + line * ldl;
-        const int base = (j - k) * R + k;
-#pragma unroll
-        for (int t = 0; t < R; ++t) d[pad(base + t * Ls)] = v[t];
-    }
-    __syncthreads();
-}
-
-// Transform lines held in buffer a (b is scratch of the same shape); returns
-// the buffer that holds the result.  Callers synchronise before the call; the
-// call ends with a barrier.  `tw` may point to LDS or global memory.
-template <int NTH, bool INV, typename T>
-__device__ cplx<T>* fft_lines_pp(cplx<T>* a, cplx<T>* b, int ldl, int nlines, const FftDesc& d, const cplx<T>* tw) {
-    int Ls = 1;
-    for (int s = 0; s < d.nstages; ++s) {
-        const int R = d.radix[s];
-        if (R == 8) fft_stage_pp<8, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
-        else if (R == 4) fft_stage_pp<4, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
-        else if (R == 3) fft_stage_pp<3, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
-        else fft_stage_pp<2, NTH, INV, T>(a, b, ldl, nlines, d.n, Ls, tw);
-        Ls *= R;
-        cplx<T>* t = a;
-        a = b;
-        b = t;
-    }
-    return a;
-}
-
 // Order this wavefront's LDS accesses: LDS instructions of one wavefront are
 // performed in issue order, so a compiler-level fence at wavefront scope is
 // all a wave needs between writing and re-reading its own LDS region.
@@ -291,10 +174,15 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // Wavefront-private Stockham stage: the 64 lanes of one wave transform one
 // line in place (all of the wave's reads precede its writes in program order).
 // MAXB = butterflies per lane = ceil(N / R / 64).
+//
+// Twiddles are packed by stage: the stage whose sub-transforms have length Ls
+// (radix R) reads w_N^(t k N / (Ls R)), t = 1..R-1, k = 0..Ls-1, at index
+// t * Ls + k - 1, so the stages occupy [Ls - 1, R Ls - 1) one after another
+// (N - 1 entries in all) and the lanes of a stage, which run over consecutive
+// k, read consecutive entries (no LDS bank conflicts).
 template <int R, int MAXB, bool INV, typename T>
 __device__ __forceinline__ void wfft_stage(cplx<T>* line, int N, int Ls, const cplx<T>* tw, int lane) {
     const int nbf = N / R;
-    const int step = N / (Ls * R);
     const float inv_ls = 1.0f / (float)Ls;
     cplx<T> v[MAXB][R];
     int dst[MAXB];
@@ -309,7 +197,7 @@ __device__ __forceinline__ void wfft_stage(cplx<T>* line, int N, int Ls, const c
             if (Ls > 1) {
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
-                    const cplx<T> w = tw[t * k * step];
+                    const cplx<T> w = tw[t * Ls + k - 1];
                     v[i][t] = INV ? cmulc(v[i][t], w) : cmul(v[i][t], w);
                 }
             }
