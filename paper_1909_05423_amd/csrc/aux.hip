@@ -90,18 +90,25 @@ hipError_t launch_finalize_update(const double* partial, int nper, int batch, do
 // r = scale * (f - lift - c - L_h u) in double, stored as float (lift: the face
 // values of a non-homogeneous problem, see FaceArgs; c: see ResidualArgs;
 // removing it in double keeps the float image of r at the precision of the
-// small correction it carries).  L_h: the 7-point stencil
-// of Eq. 3 with the face ghost rules (periodic wrap; Dirichlet ghost = -u of
-// the boundary cell, linear extrapolation to a zero face value; Neumann ghost
-// = u of the boundary cell).
-__device__ __forceinline__ double ghost_or(const double* p, long stride, int idx, int n, int kind_lo, int kind_hi,
-                                           int dir, double self) {
-    // neighbour at idx + dir along one axis of length n
+// small correction it carries).  L_h: the 7-point stencil of Eq. 3 with the
+// face ghost rules (periodic wrap; Dirichlet ghost = -u of the boundary cell,
+// linear extrapolation to a zero face value; Neumann ghost = u of the boundary
+// cell).
+//
+// Every neighbour is read from a valid address: past a face the thread reads
+// the periodic image, or the boundary cell itself and multiplies it by -1
+// (Dirichlet) or +1 (Neumann).  The loads then carry no branches, and the
+// values of the next plane are fetched while the current one is formed.
+struct Nbr {
+    long off;     // element offset of the value to read
+    double sgn;   // factor applied to it
+};
+
+__device__ __forceinline__ Nbr neighbour(int idx, int n, long stride, int dir, int kind) {
     const int q = idx + dir;
-    if (q >= 0 && q < n) return p[(long)dir * stride];
-    const int kind = dir < 0 ? kind_lo : kind_hi;
-    if (kind == BC_P) return p[(long)(dir < 0 ? (n - 1) : -(n - 1)) * stride];
-    return kind == BC_D ? -self : self;
+    if (q >= 0 && q < n) return {(long)dir * stride, 1.0};
+    if (kind == BC_P) return {(long)(dir < 0 ? (n - 1) : -(n - 1)) * stride, 1.0};
+    return {0, kind == BC_D ? -1.0 : 1.0};
 }
 
 // One thread per (x, y) column and a stretch of kResZ planes: the z neighbours
@@ -109,10 +116,11 @@ __device__ __forceinline__ double ghost_or(const double* p, long stride, int idx
 // caches (their lines are loaded by the neighbouring threads of the block).
 constexpr int kResZ = 16;
 
-__device__ __forceinline__ double z_ghost(double cell, double opposite, int kind) {
-    if (kind == BC_P) return opposite;
-    return kind == BC_D ? -cell : cell;
-}
+struct ResPlane {
+    double xm, xp, ym, yp;   // in-plane neighbours (ghost rule applied)
+    double up;               // the cell above (plane k + 1, ghost rule applied)
+    double f;                // source
+};
 
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, const double* __restrict__ u,
                                                   float* __restrict__ r, ResidualArgs a,
@@ -124,36 +132,49 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
     const int z0 = (blockIdx.z - b * nzc) * kResZ;
     if (i >= a.nx || j >= a.ny) return;
     const int z1 = min(z0 + kResZ, a.nz);
-    const size_t plane = (size_t)a.nx * a.ny;
+    const long plane = (long)a.nx * a.ny;
     const size_t base = (size_t)b * a.nz * plane + (size_t)j * a.nx + i;
     const double* ub = u + base;
+    const double* fb = f + base;
     const double mu = a.proj ? sc[SC_COUNT + 3 * a.batch + b] : 0.0;
     const double scale = sc[SC_SCALE];
-    // window: below, centre, above
-    double uc = ub[(size_t)z0 * plane];
-    double ud = (z0 > 0) ? ub[(size_t)(z0 - 1) * plane]
-                         : z_ghost(uc, ub[(size_t)(a.nz - 1) * plane], a.bc[4]);
+    const Nbr xm = neighbour(i, a.nx, 1, -1, a.bc[0]), xp = neighbour(i, a.nx, 1, 1, a.bc[1]);
+    const Nbr ym = neighbour(j, a.ny, a.nx, -1, a.bc[2]), yp = neighbour(j, a.ny, a.nx, 1, a.bc[3]);
+    auto load = [&](int k) {
+        const double* p = ub + (long)k * plane;
+        const Nbr zp = neighbour(k, a.nz, plane, 1, a.bc[5]);
+        ResPlane v;
+        v.xm = xm.sgn * p[xm.off];
+        v.xp = xp.sgn * p[xp.off];
+        v.ym = ym.sgn * p[ym.off];
+        v.yp = yp.sgn * p[yp.off];
+        v.up = zp.sgn * p[zp.off];
+        v.f = fb[(long)k * plane];
+        return v;
+    };
+    // window: below, centre
+    double uc = ub[(long)z0 * plane];
+    const Nbr zm = neighbour(z0, a.nz, plane, -1, a.bc[4]);
+    double ud = zm.sgn * ub[(long)z0 * plane + zm.off];
+    ResPlane cur = load(z0);
     for (int k = z0; k < z1; ++k) {
-        const double* p = ub + (size_t)k * plane;
-        const double uu = (k + 1 < a.nz) ? p[plane] : z_ghost(uc, ub[0], a.bc[5]);
+        const ResPlane nxt = load(min(k + 1, z1 - 1));   // the last pass re-reads its own plane
         // second differences as sums of first differences: neighbouring values
         // of a smooth u differ by far less than their size, so each first
         // difference is exact (Sterbenz) and the stencil's rounding error scales
         // with |L_h u| rather than with |u| / h^2
-        const double lx = (ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], -1, uc) - uc) +
-                          (ghost_or(p, 1, i, a.nx, a.bc[0], a.bc[1], 1, uc) - uc);
-        const double ly = (ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], -1, uc) - uc) +
-                          (ghost_or(p, a.nx, j, a.ny, a.bc[2], a.bc[3], 1, uc) - uc);
-        const double lz = (ud - uc) + (uu - uc);
+        const double lx = (cur.xm - uc) + (cur.xp - uc);
+        const double ly = (cur.ym - uc) + (cur.yp - uc);
+        const double lz = (ud - uc) + (cur.up - uc);
         const double lap = lx * a.ihx2 + ly * a.ihy2 + lz * a.ihz2;
-        const size_t idx = base + (size_t)k * plane;
-        double fi = f[idx];
+        double fi = cur.f;
         if (a.has_faces) fi -= face_lift(a.faces, b, i, j, k, a.nx, a.ny, a.nz);
         if (a.proj == 1) fi -= mu;
         else if (a.proj == 2 && k == 0) fi -= (double)a.nz * mu;
-        r[idx] = (float)((fi - lap) * scale);
+        r[base + (size_t)k * plane] = (float)((fi - lap) * scale);
         ud = uc;
-        uc = uu;
+        uc = cur.up;
+        cur = nxt;
     }
 }
 

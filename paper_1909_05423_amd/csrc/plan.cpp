@@ -3,7 +3,7 @@
 //
 // Host-side numerics (all double, angles reduced exactly over the integers and
 // evaluated in long double before rounding):
-//   * FFT twiddles exp(-2 pi i j / N) and the DCT twiddles exp(-i pi k / (2N));
+//   * FFT twiddles (powers of exp(-2 pi i / N), packed by stage) and the DCT twiddles exp(-i pi k / (2N));
 //   * the 1-D eigenvalues of Table eig, written -4 sin^2(t/2) / h^2 (equal to
 //     the table's -2 + 2 cos(t), without its cancellation at small t);
 //   * the reciprocal pivots of every z-system (section "Solution of the

@@ -47,7 +47,7 @@ template <typename T> struct XArgs {
     int ldl;                 // LDS line stride (padded_len(nx))
     long sstride, zstride;   // spectral array: element (b, m, z, y) at b*slots*nz*ny + m*sstride + z*zstride + y
     FftDesc fx;              // radix plan for nx
-    const cplx<T>* twx;      // exp(-2 pi i j / nx), j < nx
+    const cplx<T>* twx;      // FFT twiddles of length nx, packed by stage (wfft_stage)
     const cplx<T>* mkx;      // exp(-i pi k / (2 nx)), k < nx
 };
 
@@ -103,7 +103,7 @@ template <typename T> struct MidArgs {
     T scale;                 // hz^2 / (nx ny): all transform normalisations and the z-system scaling
     double hz2;              // hz^2 (projection constant = hz^2 * mean(f))
     FftDesc fy;
-    const cplx<T>* twy;      // exp(-2 pi i j / ny)
+    const cplx<T>* twy;      // FFT twiddles of length ny, packed by stage (wfft_stage)
     const cplx<T>* mky;      // exp(-i pi k / (2 ny))
     const int* rowoff;       // per slot: first table row
     const int* lmax;         // per slot: rows stored (z < lmax reads the table)
