@@ -29,6 +29,8 @@
 //     A_k = (Z_k + conj Z_{ny-k}) / 2 -> entry k,  B_k = (Z_k - conj Z_{ny-k}) / (2i) -> entry ny-k
 // so that every entry's real and imaginary parts are independent z-systems.
 
+#include <type_traits>
+
 #include "pp_kernels.hpp"
 
 namespace pp {
@@ -313,6 +315,84 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
 }
 
+// 512-point transform of one line by one wavefront: the radix plan of 512 is
+// three radix-8 Stockham stages (sub-transform lengths Ls = 1, 8, 64).  In
+// every stage lane j reads elements j + 64 t; the first stage has no
+// twiddles, and the last writes its outputs back to j + 64 t, the natural
+// order.  So a line whose elements y = lane + 64 t sit in a lane's registers
+// can enter the first stage without an LDS round trip, and the last stage can
+// hand its outputs to the caller in registers in the same order.  A lane's
+// twiddles of stages 2 and 3 are the same for every line: in float they stay
+// in registers (Tw512Reg), in double they are read from the LDS table
+// (Tw512Lds), whose registers the double kernel cannot spare.
+template <typename T> struct Tw512Reg {
+    cplx<T> r2[7], r3[7];
+    __device__ __forceinline__ cplx<T> s2(int t) const { return r2[t - 1]; }
+    __device__ __forceinline__ cplx<T> s3(int t) const { return r3[t - 1]; }
+};
+
+// packed table (see wfft_stage): stage Ls, factor t, index k at t Ls + k - 1
+template <typename T> struct Tw512Lds {
+    const cplx<T>* tw;
+    int lane;
+    __device__ __forceinline__ cplx<T> s2(int t) const { return tw[t * 8 + (lane & 7) - 1]; }
+    __device__ __forceinline__ cplx<T> s3(int t) const { return tw[t * 64 + lane - 1]; }
+};
+
+template <typename T> __device__ __forceinline__ Tw512Reg<T> tw512_regs(const cplx<T>* tw, int lane) {
+    const Tw512Lds<T> src{tw, lane};
+    Tw512Reg<T> w;
+#pragma unroll
+    for (int t = 1; t < 8; ++t) {
+        w.r2[t - 1] = src.s2(t);
+        w.r3[t - 1] = src.s3(t);
+    }
+    return w;
+}
+
+// stage 1 on values in registers (v[t] = element lane + 64 t), result to the line
+template <bool INV, typename T> __device__ __forceinline__ void w512_first(cplx<T> (&v)[8], cplx<T>* line, int lane) {
+    bfly8<INV, T>(v);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) line[pad(lane * 8 + t)] = v[t];
+    wave_lds_sync();
+}
+
+// stage 1 on the line, in place
+template <bool INV, typename T> __device__ __forceinline__ void w512_first_lds(cplx<T>* line, int lane) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = line[pad(lane + 64 * t)];
+    wave_lds_sync();
+    w512_first<INV, T>(v, line, lane);
+}
+
+// stage 2 on the line, in place
+template <bool INV, typename T, typename TW>
+__device__ __forceinline__ void w512_second(cplx<T>* line, const TW& w, int lane) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = line[pad(lane + 64 * t)];
+#pragma unroll
+    for (int t = 1; t < 8; ++t) v[t] = INV ? cmulc(v[t], w.s2(t)) : cmul(v[t], w.s2(t));
+    bfly8<INV, T>(v);
+    const int k = lane & 7;
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) line[pad((lane - k) * 8 + k + 8 * t)] = v[t];
+    wave_lds_sync();
+}
+
+// stage 3 from the line; the outputs stay in registers (v[t] = element lane + 64 t)
+template <bool INV, typename T, typename TW>
+__device__ __forceinline__ void w512_last(const cplx<T>* line, const TW& w, int lane, cplx<T> (&v)[8]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = line[pad(lane + 64 * t)];
+#pragma unroll
+    for (int t = 1; t < 8; ++t) v[t] = INV ? cmulc(v[t], w.s3(t)) : cmul(v[t], w.s3(t));
+    bfly8<INV, T>(v);
+}
+
 // ---------------------------------------------------------------------------
 // Pipelined z march for ny <= 512: the same stages as k_zmarch, arranged so
 // that the memory traffic of one chunk overlaps the arithmetic of another.
@@ -352,6 +432,16 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     for (int i = tid; i < ny; i += NTH) {
         twl[i] = a.twy[i];
         mkl[i] = a.mky[i];
+    }
+    // periodic y on lines of 512: the transforms take their first (forward) or
+    // last (inverse) stage in registers (w512_*)
+    const bool reg512 = FULL && a.by == BC_P;
+    using Tw512 = std::conditional_t<sizeof(T) == 4, Tw512Reg<T>, Tw512Lds<T>>;
+    Tw512 w512;
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (FULL) w512 = tw512_regs<T>(a.twy, lane);
+    } else {
+        w512 = Tw512Lds<T>{twl, lane};
     }
     cplx<T>* col = S + (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride;
     const size_t zs = (size_t)a.zstride;
@@ -428,7 +518,11 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         lds_barrier();   // the previous recurrences are done with the work buffer
         cplx<T>* line = work + wave * kSLdy;
         const bool own = FULL || wave < nl;
-        if (own) {
+        cplx<T> v[EPL];
+        if (reg512) {
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) v[k] = pre[k];
+        } else if (own) {
             // prefetched plane -> work plane, reordered for the forward transform
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
@@ -445,7 +539,23 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
             }
         }
         load_plane(min(zc + kSZ, last));
-        if (own) {
+        if (reg512) {
+            w512_first<false, T>(v, line, lane);
+            w512_second<false, T>(line, w512, lane);
+            w512_last<false, T>(line, w512, lane, v);
+            // each lane writes back the elements it read
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) line[pad(lane + 64 * t)] = v[t];
+            if (sep) {
+                wave_lds_sync();
+                for (int k = lane; k < half; k += 64) {
+                    if (k == 0 || 2 * k >= ny) continue;
+                    const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
+                    line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
+                    line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+                }
+            }
+        } else if (own) {
             wave_lds_sync();
             wfft<EPL, false, T>(line, a.fy, twl, lane);
             if (a.by != BC_P) {
@@ -586,8 +696,16 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
                 }
             }
             wave_lds_sync();
-            wfft<EPL, true, T>(line, a.fy, twl, lane);
             cplx<T>* dst = col + (size_t)(zc + wave) * zs;
+            if (reg512) {
+                cplx<T> v[EPL];
+                w512_first_lds<true, T>(line, lane);
+                w512_second<true, T>(line, w512, lane);
+                w512_last<true, T>(line, w512, lane, v);
+#pragma unroll
+                for (int t = 0; t < EPL; ++t) dst[lane + 64 * t] = v[t];
+            } else {
+            wfft<EPL, true, T>(line, a.fy, twl, lane);
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 const int y = lane + 64 * k;
@@ -598,6 +716,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
                     if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
                     dst[y] = v;
                 }
+            }
             }
         }
     };
