@@ -394,37 +394,41 @@ __device__ __forceinline__ void w512_last(const cplx<T>* line, const TW& w, int 
 }
 
 // ---------------------------------------------------------------------------
-// Pipelined z march for ny <= 512: the same stages as k_zmarch, arranged so
-// that the memory traffic of one chunk overlaps the arithmetic of another.
+// Pipelined z march for y lines of up to NYMAX = 512 (both precisions) or
+// 1024 (float, whose chunk of 1024-long planes fits in LDS): the same stages as
+// k_zmarch, arranged so that the memory traffic of one chunk overlaps the
+// arithmetic of another.
 //
-// A chunk is 8 planes, one per wavefront.  Upward, a lane prefetches its share
-// of its wavefront's plane of the next chunk into registers while the current
+// A chunk is 8 planes, one per wavefront; a lane holds elements y = lane + 64 k
+// of its wavefront's plane, and a thread owns the z recurrences of entries
+// e = tid + 512 o (o < NYMAX / 512).  Upward, a lane prefetches its share of
+// its wavefront's plane of the next chunk into registers while the current
 // chunk is transformed and eliminated; the pivots of the next chunk are
-// fetched after the current recurrences.  Downward, a thread prefetches its own
-// entry of the 8 planes of the next chunk (the eliminated right-hand sides),
-// so back substitution runs from registers, and each wavefront then transforms
-// and stores one plane.
+// fetched after the current recurrences.  Downward, a thread prefetches its
+// own entries of the 8 planes of the next chunk (the eliminated right-hand
+// sides), so back substitution runs from registers, and each wavefront then
+// transforms and stores one plane.
 //
 // The order of issue is chosen so that, with in-order completion of vector
 // memory operations, every wait retires only what it needs: at each point of
 // use, the operations issued after the awaited load are a fixed set (one
-// chunk's stores, or one chunk's prefetch).  FULL (ny == 512, nz a multiple of
-// 8) removes every data-dependent branch around memory instructions, so the
+// chunk's stores, or one chunk's prefetch).  FULL (ny == NYMAX, nz a multiple
+// of 8) removes every data-dependent branch around memory instructions, so the
 // compiler can count them exactly; barriers order LDS only.
 constexpr int kSZ = 8;        // planes per chunk = wavefronts per workgroup
-constexpr int kSNy = 512;     // longest y line of the pipelined march
-constexpr int kSLdy = 576;    // work-buffer plane stride (>= padded_len(512))
 
-
-template <typename T, bool FULL, bool PERZ>
+template <typename T, int NYMAX, bool FULL, bool PERZ>
 __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
-    __shared__ __align__(16) cplx<T> work[kSZ * kSLdy];
-    __shared__ __align__(16) cplx<T> twl[kSNy];
-    __shared__ __align__(16) cplx<T> mkl[kSNy];
     constexpr int NTH = 512;
-    constexpr int EPL = kSNy / 64;               // plane elements per lane
+    constexpr int EPL = NYMAX / 64;              // plane elements per lane
+    constexpr int OWN = NYMAX / NTH;             // z-recurrence entries per thread
+    constexpr int LDY = NYMAX + NYMAX / 8;       // work-buffer plane stride (>= padded_len(NYMAX))
+    static_assert(EPL == kSZ * OWN, "one prefetch buffer serves both directions");
+    __shared__ __align__(16) cplx<T> work[kSZ * LDY];
+    __shared__ __align__(16) cplx<T> twl[NYMAX];
+    __shared__ __align__(16) cplx<T> mkl[NYMAX];
     const int m = blockIdx.x, b = blockIdx.y;
-    const int ny = FULL ? kSNy : a.ny;
+    const int ny = FULL ? NYMAX : a.ny;
     const int nz = a.nz;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -435,11 +439,12 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     }
     // periodic y on lines of 512: the transforms take their first (forward) or
     // last (inverse) stage in registers (w512_*)
-    const bool reg512 = FULL && a.by == BC_P;
+    constexpr bool R512 = FULL && NYMAX == 512;
+    const bool reg512 = R512 && a.by == BC_P;
     using Tw512 = std::conditional_t<sizeof(T) == 4, Tw512Reg<T>, Tw512Lds<T>>;
     Tw512 w512;
     if constexpr (sizeof(T) == 4) {
-        if constexpr (FULL) w512 = tw512_regs<T>(a.twy, lane);
+        if constexpr (R512) w512 = tw512_regs<T>(a.twy, lane);
     } else {
         w512 = Tw512Lds<T>{twl, lane};
     }
@@ -455,46 +460,59 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     const int nchunks = (nz + kSZ - 1) / kSZ;
     const int last = (nchunks - 1) * kSZ;
 
-    // this thread's z-recurrence entry (threads past ny read a valid dummy)
-    const int e = tid;
-    const bool live = FULL || e < ny;
-    const int ec = live ? e : 0;
-    const cplx<T> winf = a.winf[(size_t)m * ny + ec];
-    const cplx<T> wlast = a.wlast[(size_t)m * ny + ec];
+    // this thread's z-recurrence entries (entries past ny read a valid dummy)
+    int ec[OWN];
+    bool live[OWN];
+    cplx<T> winf[OWN], wlast[OWN];
     // periodic z: y_0 accumulated on the way up, the correction c = (y_0 +
     // y_{n-1}/gamma)/den at the turn, and q_z rebuilt on the way down (the
     // Sherman-Morrison rows decay from z = 0, so only the first chunks read them)
-    cplx<T> y0 = mk<T>(T(0), T(0)), corr = y0, qnext = y0;
+    cplx<T> y0[OWN], corr[OWN], qnext[OWN];
     int alen = 0, aoff = 0, qlen = 0, qoff = 0;
     if constexpr (PERZ) {
         alen = a.alen[m];
         aoff = a.aoff[m];
         qlen = a.qlen[m];
         qoff = a.qoff[m];
-        qnext = a.qlast[(size_t)m * ny + ec];
+    }
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        const int e = tid + NTH * o;
+        live[o] = FULL || e < ny;
+        ec[o] = live[o] ? e : 0;
+        winf[o] = a.winf[(size_t)m * ny + ec[o]];
+        wlast[o] = a.wlast[(size_t)m * ny + ec[o]];
+        y0[o] = mk<T>(T(0), T(0));
+        corr[o] = y0[o];
+        qnext[o] = y0[o];
+        if constexpr (PERZ) qnext[o] = a.qlast[(size_t)m * ny + ec[o]];
     }
 
-    // reciprocal pivots of planes zc .. zc+7 for entry e (planes past the
-    // slot's rows read the first table element, which always exists; the value
-    // then comes from winf / wlast)
-    cplx<T> pv[kSZ];
-    const cplx<T>* wrows = a.wrows + ec;
-    auto load_piv = [&](int zc) {
+    // reciprocal pivots of planes zc .. zc+7 for the thread's entries (planes
+    // past the slot's rows read the first table element, which always exists;
+    // the value then comes from winf / wlast); plane l, entry o at l * OWN + o
+    cplx<T> pv[kSZ * OWN];
+    auto load_piv = [&](int zc) __attribute__((always_inline)) {
 #pragma unroll
         for (int l = 0; l < kSZ; ++l) {
             const int z = zc + l;
-            // past the slot's rows every lane reads the same element, one cache line per wavefront
-            const cplx<T>* src = (z < lmax) ? wrows + (size_t)(roff + z) * ny : a.wrows;
-            pv[l] = *src;
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) {
+                // past the slot's rows every lane reads the same element, one cache line per wavefront
+                const cplx<T>* src = (z < lmax) ? a.wrows + (size_t)(roff + z) * ny + ec[o] : a.wrows;
+                pv[l * OWN + o] = *src;
+            }
         }
     };
-    auto pivot = [&](int z, int l) -> cplx<T> {
-        if (z == nz - 1) return wlast;
-        return (z < lmax) ? pv[l] : winf;
+    // (component-wise selects between values, so that the arrays stay in registers)
+    auto pivot = [&](int z, int l, int o) __attribute__((always_inline)) -> cplx<T> {
+        const cplx<T> p = pv[l * OWN + o], wi = winf[o], wl = wlast[o];
+        const bool lastrow = (z == nz - 1), tab = (z < lmax);
+        return mk<T>(lastrow ? wl.x : (tab ? p.x : wi.x), lastrow ? wl.y : (tab ? p.y : wi.y));
     };
     // upward prefetch: elements y = lane + 64 k of plane zc + wave (clamped to the last plane)
     cplx<T> pre[EPL];
-    auto load_plane = [&](int zc) {
+    auto load_plane = [&](int zc) __attribute__((always_inline)) {
         const cplx<T>* src = col + (size_t)min(zc + wave, nz - 1) * zs;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
@@ -502,21 +520,26 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
             pre[k] = src[(FULL || y < ny) ? y : 0];
         }
     };
-    // downward prefetch: entry e of planes zc .. zc+7 (clamped to the last plane)
-    auto load_entry = [&](int zc) {
+    // downward prefetch: the thread's entries of planes zc .. zc+7 (clamped to the last plane)
+    auto load_entry = [&](int zc) __attribute__((always_inline)) {
 #pragma unroll
-        for (int l = 0; l < kSZ; ++l) pre[l] = col[(size_t)min(zc + l, nz - 1) * zs + ec];
+        for (int l = 0; l < kSZ; ++l) {
+#pragma unroll
+            for (int o = 0; o < OWN; ++o) pre[l * OWN + o] = col[(size_t)min(zc + l, nz - 1) * zs + ec[o]];
+        }
     };
 
     // ------------------------------------------------------------- upward
-    cplx<T> st = mk<T>(T(0), T(0));
+    cplx<T> st[OWN];
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) st[o] = mk<T>(T(0), T(0));
     load_plane(0);
     load_piv(0);
-    auto up_chunk = [&](int c) {
+    auto up_chunk = [&](int c) __attribute__((always_inline)) {
         const int zc = c * kSZ;
         const int nl = FULL ? kSZ : min(kSZ, nz - zc);
         lds_barrier();   // the previous recurrences are done with the work buffer
-        cplx<T>* line = work + wave * kSLdy;
+        cplx<T>* line = work + wave * LDY;
         const bool own = FULL || wave < nl;
         cplx<T> v[EPL];
         if (reg512) {
@@ -528,21 +551,23 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
             for (int k = 0; k < EPL; ++k) {
                 const int y = lane + 64 * k;
                 if (FULL || y < ny) {
-                    cplx<T> v = pre[k];
+                    cplx<T> x = pre[k];
                     int pos = y;
                     if (a.by != BC_P) {
                         pos = makhoul_pos(y, ny);
-                        if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
+                        if (a.by == BC_D && (y & 1)) x = mk<T>(-x.x, -x.y);
                     }
-                    line[pad(pos)] = v;
+                    line[pad(pos)] = x;
                 }
             }
         }
         load_plane(min(zc + kSZ, last));
         if (reg512) {
-            w512_first<false, T>(v, line, lane);
-            w512_second<false, T>(line, w512, lane);
-            w512_last<false, T>(line, w512, lane, v);
+            if constexpr (R512) {
+                w512_first<false, T>(v, line, lane);
+                w512_second<false, T>(line, w512, lane);
+                w512_last<false, T>(line, w512, lane, v);
+            }
             // each lane writes back the elements it read
 #pragma unroll
             for (int t = 0; t < EPL; ++t) line[pad(lane + 64 * t)] = v[t];
@@ -583,34 +608,37 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         }
         lds_barrier();
         // forward elimination over the chunk; eliminated right-hand sides go to HBM
-        if (live) {
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            if (!live[o]) continue;
+            const int e = ec[o];
             cplx<T> al[PERZ ? kSZ : 1];
             if constexpr (PERZ) {
                 if (zc < alen) {
 #pragma unroll
                     for (int l = 0; l < kSZ; ++l)
-                        al[l] = (zc + l < alen) ? a.arows[(size_t)(aoff + zc + l) * ny + ec] : mk<T>(T(0), T(0));
+                        al[l] = (zc + l < alen) ? a.arows[(size_t)(aoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
                 }
             }
-            cplx<T> prev = st;
+            cplx<T> prev = st[o];
 #pragma unroll
             for (int l = 0; l < kSZ; ++l) {
                 if (FULL || l < nl) {
                     const int z = zc + l;
-                    const cplx<T> w = pivot(z, l);
-                    cplx<T> d = cscale(work[l * kSLdy + pad(e)], scale);
+                    const cplx<T> w = pivot(z, l, o);
+                    cplx<T> d = cscale(work[l * LDY + pad(e)], scale);
                     if (sing && e == 0) d.x -= proj;
                     if constexpr (PERZ) {
                         if (zc < alen) {
-                            y0.x += al[l].x * d.x;
-                            y0.y += al[l].y * d.y;
+                            y0[o].x += al[l].x * d.x;
+                            y0[o].y += al[l].y * d.y;
                         }
                     }
                     prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
                     col[(size_t)z * zs + e] = prev;
                 }
             }
-            st = prev;
+            st[o] = prev;
         }
         load_piv(min(zc + kSZ, last));   // the last chunk reloads its own pivots for the way down
     };
@@ -621,52 +649,58 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
 
     // ----------------------------------------------------------- downward
     // the top chunk's eliminated right-hand sides were stored by this thread
-    // (same entry, same addresses): read them back in program order
+    // (same entries, same addresses): read them back in program order
     load_entry(last);
-    if constexpr (PERZ) {
-        // st is y_{n-1}, the last eliminated value
-        const cplx<T> ig = a.inv_gamma[(size_t)m * ny + ec], id = a.inv_den[(size_t)m * ny + ec];
-        corr = mk<T>((y0.x + st.x * ig.x) * id.x, (y0.y + st.y * ig.y) * id.y);
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        if constexpr (PERZ) {
+            // st is y_{n-1}, the last eliminated value
+            const cplx<T> ig = a.inv_gamma[(size_t)m * ny + ec[o]], id = a.inv_den[(size_t)m * ny + ec[o]];
+            corr[o] = mk<T>((y0[o].x + st[o].x * ig.x) * id.x, (y0[o].y + st[o].y * ig.y) * id.y);
+        }
+        st[o] = mk<T>(T(0), T(0));
     }
-    st = mk<T>(T(0), T(0));
     double csum = 0.0;
-    auto down_chunk = [&](int c) {
+    auto down_chunk = [&](int c) __attribute__((always_inline)) {
         const int zc = c * kSZ;
         const int nl = FULL ? kSZ : min(kSZ, nz - zc);
         lds_barrier();   // the previous inverse transforms are done with the work buffer
         // back substitution over the chunk, from registers into the work buffer
-        if (live) {
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            if (!live[o]) continue;
+            const int e = ec[o];
             cplx<T> qv[PERZ ? kSZ : 1];
             if constexpr (PERZ) {
                 if (zc < qlen) {
 #pragma unroll
                     for (int l = 0; l < kSZ; ++l)
-                        qv[l] = (zc + l < qlen) ? a.qrows[(size_t)(qoff + zc + l) * ny + ec] : mk<T>(T(0), T(0));
+                        qv[l] = (zc + l < qlen) ? a.qrows[(size_t)(qoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
                 }
             }
-            cplx<T> nxt = st;
+            cplx<T> nxt = st[o];
 #pragma unroll
             for (int j = 0; j < kSZ; ++j) {
                 const int l = kSZ - 1 - j;
                 if (FULL || l < nl) {
                     const int z = zc + l;
-                    const cplx<T> w = pivot(z, l);
-                    const cplx<T> dp = pre[l];
+                    const cplx<T> w = pivot(z, l, o);
+                    const cplx<T> dp = pre[l * OWN + o];
                     nxt = mk<T>(dp.x - w.x * nxt.x, dp.y - w.y * nxt.y);
                     cplx<T> un = nxt;
                     if constexpr (PERZ) {
                         // q_z of the rank-one vector, then u_z = y_z - c q_z
                         if (z != nz - 1) {
                             const cplx<T> qp = (zc < qlen) ? qv[l] : mk<T>(T(0), T(0));
-                            qnext = mk<T>(qp.x - w.x * qnext.x, qp.y - w.y * qnext.y);
+                            qnext[o] = mk<T>(qp.x - w.x * qnext[o].x, qp.y - w.y * qnext[o].y);
                         }
-                        un = mk<T>(nxt.x - corr.x * qnext.x, nxt.y - corr.y * qnext.y);
+                        un = mk<T>(nxt.x - corr[o].x * qnext[o].x, nxt.y - corr[o].y * qnext[o].y);
                     }
-                    work[l * kSLdy + pad(e)] = un;
+                    work[l * LDY + pad(e)] = un;
                     if (sing && e == 0) csum += (double)un.x;
                 }
             }
-            st = nxt;
+            st[o] = nxt;
         }
         lds_barrier();
         const int zn = zc >= kSZ ? zc - kSZ : 0;
@@ -674,7 +708,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         load_piv(zn);
         // inverse y transform of this wave's plane, written straight to HBM
         if (FULL || wave < nl) {
-            cplx<T>* line = work + wave * kSLdy;
+            cplx<T>* line = work + wave * LDY;
             if (a.by != BC_P) {
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0) continue;
@@ -699,24 +733,26 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
             cplx<T>* dst = col + (size_t)(zc + wave) * zs;
             if (reg512) {
                 cplx<T> v[EPL];
-                w512_first_lds<true, T>(line, lane);
-                w512_second<true, T>(line, w512, lane);
-                w512_last<true, T>(line, w512, lane, v);
+                if constexpr (R512) {
+                    w512_first_lds<true, T>(line, lane);
+                    w512_second<true, T>(line, w512, lane);
+                    w512_last<true, T>(line, w512, lane, v);
+                }
 #pragma unroll
                 for (int t = 0; t < EPL; ++t) dst[lane + 64 * t] = v[t];
             } else {
-            wfft<EPL, true, T>(line, a.fy, twl, lane);
+                wfft<EPL, true, T>(line, a.fy, twl, lane);
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) {
-                const int y = lane + 64 * k;
-                if (FULL || y < ny) {
-                    int pos = y;
-                    if (a.by != BC_P) pos = makhoul_pos(y, ny);
-                    cplx<T> v = line[pad(pos)];
-                    if (a.by == BC_D && (y & 1)) v = mk<T>(-v.x, -v.y);
-                    dst[y] = v;
+                for (int k = 0; k < EPL; ++k) {
+                    const int y = lane + 64 * k;
+                    if (FULL || y < ny) {
+                        int pos = y;
+                        if (a.by != BC_P) pos = makhoul_pos(y, ny);
+                        cplx<T> x = line[pad(pos)];
+                        if (a.by == BC_D && (y & 1)) x = mk<T>(-x.x, -x.y);
+                        dst[y] = x;
+                    }
                 }
-            }
             }
         }
     };
@@ -725,11 +761,17 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
 }
 
-template <typename T, bool FULL>
+template <typename T, int NYMAX, bool FULL>
 static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, FULL, true>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
-    else hipLaunchKernelGGL((k_zpipe<T, FULL, false>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
+    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, NYMAX, FULL, true>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
+    else hipLaunchKernelGGL((k_zpipe<T, NYMAX, FULL, false>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
     return hipGetLastError();
+}
+
+template <typename T, int NYMAX>
+static hipError_t launch_pipe_any(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+    if (a.ny == NYMAX && a.nz % kSZ == 0) return launch_pipe<T, NYMAX, true>(S, a, batch, s);
+    return launch_pipe<T, NYMAX, false>(S, a, batch, s);
 }
 
 template <typename T, int RMAX, int OWN>
@@ -745,14 +787,15 @@ static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, h
     return hipGetLastError();
 }
 
-// ny <= 512: the pipelined march; longer lines: k_zmarch with 16 values per lane and
-// two z entries per thread (ny <= 1024) or 32 and 4 (ny <= 2048).
+// ny <= 512, and ny <= 1024 in float: the pipelined march; longer lines:
+// k_zmarch with 16 values per lane and two z entries per thread (ny <= 1024) or
+// 32 and 4 (ny <= 2048).
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     if (a.zsolver == 1) return launch_mid_pcr<T>(S, a, batch, s);
-    if (a.ny <= kSNy) {
-        if (a.ny == kSNy && a.nz % kSZ == 0) return launch_pipe<T, true>(S, a, batch, s);
-        return launch_pipe<T, false>(S, a, batch, s);
+    if (a.ny <= 512) return launch_pipe_any<T, 512>(S, a, batch, s);
+    if constexpr (sizeof(T) == 4) {
+        if (a.ny <= 1024) return launch_pipe_any<T, 1024>(S, a, batch, s);
     }
     if (a.ny <= 1024) return launch_mid_shape<T, 16, 2>(S, a, batch, s);
     return launch_mid_shape<T, 32, 4>(S, a, batch, s);
