@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
         v.ym = ym.sgn * p[ym.off];
         v.yp = yp.sgn * p[yp.off];
         v.up = zp.sgn * p[zp.off];
-        v.f = fb[(long)k * plane];
+        v.f = ld_stream(fb + (long)k * plane);
         return v;
     };
     // window: below, centre
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
         if (a.has_faces) fi -= face_lift(a.faces, b, i, j, k, a.nx, a.ny, a.nz);
         if (a.proj == 1) fi -= mu;
         else if (a.proj == 2 && k == 0) fi -= (double)a.nz * mu;
-        r[base + (size_t)k * plane] = (float)((fi - lap) * scale);
+        st_stream(r + base + (size_t)k * plane, (float)((fi - lap) * scale));
         ud = uc;
         uc = cur.up;
         cur = nxt;

@@ -16,6 +16,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace pp {
 
@@ -154,6 +155,34 @@ struct FftDesc {
 };
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Streaming accesses (non-temporal: the caches do not keep the line) for data
+// a kernel touches once and that no later kernel reads soon enough to find in
+// a cache.  Used where measured to help: the source rows of the forward x
+// kernel, the solution rows of the inverse, the refinement residual's source
+// and output, and the float spectra written by the forward x kernel.
+// (Complex values go through the two-element native vector of their type.)
+template <typename V> __device__ __forceinline__ V ld_stream(const V* p) {
+    if constexpr (std::is_arithmetic_v<V>) {
+        return __builtin_nontemporal_load(p);
+    } else {
+        using N = typename V::Native_vec_;
+        const N n = __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
+        V r;
+        r.x = n[0];
+        r.y = n[1];
+        return r;
+    }
+}
+template <typename V> __device__ __forceinline__ void st_stream(V* p, const V& v) {
+    if constexpr (std::is_arithmetic_v<V>) {
+        __builtin_nontemporal_store(v, p);
+    } else {
+        using N = typename V::Native_vec_;
+        const N n = {v.x, v.y};
+        __builtin_nontemporal_store(n, reinterpret_cast<N*>(p));
+    }
+}
 
 // Order this wavefront's LDS accesses: LDS instructions of one wavefront are
 // performed in issue order, so a compiler-level fence at wavefront scope is

@@ -62,6 +62,14 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Store of one spectral value by the forward x kernel.  Float spectra are
+// streamed past the caches; double spectra are stored normally (measured: the
+// streaming store made the double solve slower and the float one faster).
+template <typename T> __device__ __forceinline__ void put_spec(cplx<T>* p, const cplx<T>& v) {
+    if constexpr (sizeof(T) == 4) st_stream(p, v);
+    else *p = v;
+}
+
 // Forward x kernel, persistent: each workgroup walks row blocks
 // blockIdx.x, blockIdx.x + gridDim.x, ...; the rows of the next block are in
 // flight into registers while the current one is transformed.  Each wavefront
@@ -120,14 +128,14 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
             const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
             const int ya = xb.y0 + 2 * j;
             if (FULL) {
-                ra[r] = src[(size_t)ya * nx + n];
-                rb[r] = src[(size_t)(ya + 1) * nx + n];
+                ra[r] = ld_stream(src + (size_t)ya * nx + n);
+                rb[r] = ld_stream(src + (size_t)(ya + 1) * nx + n);
             } else {
                 ra[r] = Tin(0);
                 rb[r] = Tin(0);
                 if (j < nlines && n < nx) {
-                    if (ya < ny) ra[r] = src[(size_t)ya * nx + n];
-                    if (ya + 1 < ny) rb[r] = src[(size_t)(ya + 1) * nx + n];
+                    if (ya < ny) ra[r] = ld_stream(src + (size_t)ya * nx + n);
+                    if (ya + 1 < ny) rb[r] = ld_stream(src + (size_t)(ya + 1) * nx + n);
                 }
             }
         }
@@ -281,8 +289,8 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                 cplx<T> oa, ob;
                 column(m, j, oa, ob);
                 const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
-                dstS[col + ya] = oa;
-                dstS[col + ya + 1] = ob;
+                put_spec<T>(dstS + col + ya, oa);
+                put_spec<T>(dstS + col + ya + 1, ob);
             }
         } else {
             for (int i = tid; i < a.slots * nlines; i += NTH) {
@@ -291,8 +299,8 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                 cplx<T> oa, ob;
                 column(m, j, oa, ob);
                 const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
-                if (ya < ny) dstS[col + ya] = oa;
-                if (yb < ny) dstS[col + yb] = ob;
+                if (ya < ny) put_spec<T>(dstS + col + ya, oa);
+                if (yb < ny) put_spec<T>(dstS + col + yb, ob);
             }
         }
     };
@@ -479,11 +487,11 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                         const T v = part ? c.y : c.x;
                         const size_t idx = (size_t)y * nx + n;
                         if (MODE == XINV_STORE) {
-                            dst[idx] = (Tout)((double)v - sh);
+                            st_stream(dst + idx, (Tout)((double)v - sh));
                         } else {
                             const double d = ((double)v - sh) * inv_scale;
                             const double un = uo[UR > 1 ? 2 * k + part : 0] + d - gshift;   // uo = 0 for XINV_FIRST
-                            dst[idx] = (Tout)un;
+                            st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
                             dmax = fmax(dmax, fabs(d));
                             umax = fmax(umax, fabs(un));
@@ -503,11 +511,11 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                         const T v = part ? c.y : c.x;
                         const size_t idx = (size_t)y * nx + n;
                         if (MODE == XINV_STORE) {
-                            dst[idx] = (Tout)((double)v - sh);
+                            st_stream(dst + idx, (Tout)((double)v - sh));
                         } else {
                             const double d = ((double)v - sh) * inv_scale;
                             const double un = (MODE == XINV_UPDATE ? (double)dst[idx] : 0.0) + d - gshift;
-                            dst[idx] = (Tout)un;
+                            st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
                             dmax = fmax(dmax, fabs(d));
                             umax = fmax(umax, fabs(un));
