@@ -106,6 +106,11 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
     }
     const int epl = FULL ? RMAX : (nx + 63) >> 6;
     const float inv_epl = 1.0f / (float)epl, inv_nl = 1.0f / (float)nlines;
+    // periodic rows of 512 without face values, double spectra: the
+    // transform's first stage runs on the row registers (w512_first; in float
+    // the extra registers cost more occupancy than the LDS round trip saves)
+    constexpr bool R512 = FULL && RMAX == 8 && !FACES && sizeof(T) == 8;
+    const bool reg512 = R512 && a.bx == BC_P;
 
     // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
     Tin ra[RMAX], rb[RMAX];
@@ -196,6 +201,7 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
             cur_b = xb.b;
         }
         lds_barrier();   // the previous column writes are done reading the lines (and the twiddles are in)
+        cplx<T> vf[R512 ? 8 : 1];   // periodic rows of 512: the packed line stays in registers
         // 1. registers -> own packed lines (row 2j real part, row 2j+1 imaginary part),
         //    pre-processed for the x transform; face values lifted into the source;
         //    wavefront sums of the (lifted) source
@@ -227,7 +233,8 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
                         vb = -vb;
                     }
                 }
-                lds[j * ldl + pad(pos)] = mk<T>(va, vb);
+                if (reg512) vf[R512 ? r : 0] = mk<T>(va, vb);
+                else lds[j * ldl + pad(pos)] = mk<T>(va, vb);
             }
         }
         // the remaining face lifts, applied to the lines in place: y and z faces
@@ -267,7 +274,19 @@ __global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>
         const int nxt = blk + (int)gridDim.x;
         fetch(nxt < nblocks ? nxt : blk);
         // 2. complex FFT of every own line (FULL: exactly one)
-        if (FULL) {
+        if (reg512) {
+            if constexpr (R512) {
+                // first stage on the row registers; the result goes back to the
+                // line in natural order for the column writes
+                cplx<T>* line = lds + wave * ldl;
+                const Tw512Lds<T> tw{twl, lane};
+                w512_first<false, T>(vf, line, lane);
+                w512_second<false, T>(line, tw, lane);
+                w512_last<false, T>(line, tw, lane, vf);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) line[pad(lane + 64 * t)] = vf[t];
+            }
+        } else if (FULL) {
             wave_lds_sync();
             wfft<RMAX, false, T>(lds + wave * ldl, a.fx, twl, lane);
         } else {
@@ -328,6 +347,9 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                                               const double* __restrict__ shift, const double* __restrict__ scalars,
                                               int gauge_region, double* __restrict__ partial, int nblocks) {
     constexpr bool UPD = (MODE != XINV_STORE);   // refinement update (partials, double output)
+    // rows of 512, double spectra: w512_* stages when x is periodic (in float
+    // the extra registers cost more occupancy than the LDS round trip saves)
+    constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NW = NTH / 64;
     constexpr int PAIRS = RMAX / 2;    // (slot, row pair) gathers per thread: slots * nlines <= NTH * PAIRS
@@ -472,14 +494,30 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                 }
             }
             wave_lds_sync();
-            wfft<RMAX, true, T>(line, a.fx, twl, lane);
+            // periodic rows of 512: the last stage's outputs stay in registers,
+            // in the order the row writes take them (see w512_last)
+            cplx<T> vl[R512 ? 8 : 1];
+            if constexpr (R512) {
+                if (a.bx == BC_P) {
+                    const Tw512Lds<T> tw{twl, lane};
+                    w512_first_lds<true, T>(line, lane);
+                    w512_second<true, T>(line, tw, lane);
+                    w512_last<true, T>(line, tw, lane, vl);
+                } else {
+                    wfft<RMAX, true, T>(line, a.fx, twl, lane);
+                }
+            } else {
+                wfft<RMAX, true, T>(line, a.fx, twl, lane);
+            }
             if (FULL) {
 #pragma unroll
                 for (int k = 0; k < RMAX; ++k) {
                     const int n = lane + 64 * k;
                     int pos = n;
                     if (a.bx != BC_P) pos = makhoul_pos(n, nx);
-                    cplx<T> c = line[pad(pos)];
+                    cplx<T> c;
+                    if constexpr (R512) c = (a.bx == BC_P) ? vl[k] : line[pad(pos)];
+                    else c = line[pad(pos)];
                     if (a.bx == BC_D && (n & 1)) c = mk<T>(-c.x, -c.y);
 #pragma unroll
                     for (int part = 0; part < 2; ++part) {

@@ -315,84 +315,6 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
 }
 
-// 512-point transform of one line by one wavefront: the radix plan of 512 is
-// three radix-8 Stockham stages (sub-transform lengths Ls = 1, 8, 64).  In
-// every stage lane j reads elements j + 64 t; the first stage has no
-// twiddles, and the last writes its outputs back to j + 64 t, the natural
-// order.  So a line whose elements y = lane + 64 t sit in a lane's registers
-// can enter the first stage without an LDS round trip, and the last stage can
-// hand its outputs to the caller in registers in the same order.  A lane's
-// twiddles of stages 2 and 3 are the same for every line: in float they stay
-// in registers (Tw512Reg), in double they are read from the LDS table
-// (Tw512Lds), whose registers the double kernel cannot spare.
-template <typename T> struct Tw512Reg {
-    cplx<T> r2[7], r3[7];
-    __device__ __forceinline__ cplx<T> s2(int t) const { return r2[t - 1]; }
-    __device__ __forceinline__ cplx<T> s3(int t) const { return r3[t - 1]; }
-};
-
-// packed table (see wfft_stage): stage Ls, factor t, index k at t Ls + k - 1
-template <typename T> struct Tw512Lds {
-    const cplx<T>* tw;
-    int lane;
-    __device__ __forceinline__ cplx<T> s2(int t) const { return tw[t * 8 + (lane & 7) - 1]; }
-    __device__ __forceinline__ cplx<T> s3(int t) const { return tw[t * 64 + lane - 1]; }
-};
-
-template <typename T> __device__ __forceinline__ Tw512Reg<T> tw512_regs(const cplx<T>* tw, int lane) {
-    const Tw512Lds<T> src{tw, lane};
-    Tw512Reg<T> w;
-#pragma unroll
-    for (int t = 1; t < 8; ++t) {
-        w.r2[t - 1] = src.s2(t);
-        w.r3[t - 1] = src.s3(t);
-    }
-    return w;
-}
-
-// stage 1 on values in registers (v[t] = element lane + 64 t), result to the line
-template <bool INV, typename T> __device__ __forceinline__ void w512_first(cplx<T> (&v)[8], cplx<T>* line, int lane) {
-    bfly8<INV, T>(v);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) line[pad(lane * 8 + t)] = v[t];
-    wave_lds_sync();
-}
-
-// stage 1 on the line, in place
-template <bool INV, typename T> __device__ __forceinline__ void w512_first_lds(cplx<T>* line, int lane) {
-    cplx<T> v[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = line[pad(lane + 64 * t)];
-    wave_lds_sync();
-    w512_first<INV, T>(v, line, lane);
-}
-
-// stage 2 on the line, in place
-template <bool INV, typename T, typename TW>
-__device__ __forceinline__ void w512_second(cplx<T>* line, const TW& w, int lane) {
-    cplx<T> v[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = line[pad(lane + 64 * t)];
-#pragma unroll
-    for (int t = 1; t < 8; ++t) v[t] = INV ? cmulc(v[t], w.s2(t)) : cmul(v[t], w.s2(t));
-    bfly8<INV, T>(v);
-    const int k = lane & 7;
-    wave_lds_sync();
-#pragma unroll
-    for (int t = 0; t < 8; ++t) line[pad((lane - k) * 8 + k + 8 * t)] = v[t];
-    wave_lds_sync();
-}
-
-// stage 3 from the line; the outputs stay in registers (v[t] = element lane + 64 t)
-template <bool INV, typename T, typename TW>
-__device__ __forceinline__ void w512_last(const cplx<T>* line, const TW& w, int lane, cplx<T> (&v)[8]) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = line[pad(lane + 64 * t)];
-#pragma unroll
-    for (int t = 1; t < 8; ++t) v[t] = INV ? cmulc(v[t], w.s3(t)) : cmul(v[t], w.s3(t));
-    bfly8<INV, T>(v);
-}
-
 // ---------------------------------------------------------------------------
 // Pipelined z march for y lines of up to NYMAX = 512 (both precisions) or
 // 1024 (float, whose chunk of 1024-long planes fits in LDS): the same stages as
