@@ -84,8 +84,17 @@ template <typename T> __device__ __forceinline__ void put_spec(cplx<T>* p, const
 // wavefront, ny a multiple of the block height) has no data-dependent branch
 // around a memory instruction, so that count is exact; the first block is
 // issued outside the loop so every pass through it sees the same sequence.
+// Minimum waves per SIMD the compiler must leave room for.  2 for the
+// all-float forward kernel (on rows of 1024 it would otherwise take every
+// register and run one wave per SIMD; measured 1.64 -> 1.21 ms at
+// 1024 x 1024 x 512) and for the double kernel on rows of 512 (4 registers
+// over the budget of two waves); no constraint elsewhere (the other kernels
+// with double data spill under it).
+template <typename T, typename Tin, int RMAX>
+constexpr int kXfwdMinWaves = ((sizeof(T) == 4 && sizeof(Tin) == 4) || (sizeof(T) == 8 && RMAX == 8)) ? 2 : 1;
+
 template <typename T, typename Tin, int NTH, int RMAX, bool FULL, bool FACES>
-__global__ __launch_bounds__(NTH) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWaves<T, Tin, RMAX>))) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
                                               double* __restrict__ partial, XArgs<T> a, int nblocks,
                                               FaceArgs<Tin> fa) {
     extern __shared__ __align__(16) unsigned char smem[];
