@@ -560,10 +560,11 @@ pp_status collect(pp_plan p) {
         if ((call) != hipSuccess) return PP_ERR_HIP; \
     } while (0)
 
-// Partial records per batch entry written by the x kernels on this device
-// (<= p->nper, which sizes the partial region of the workspace).
-int x_records(pp_plan p) {
-    return pp::x_grid(pp::x_blocks(p->ny, p->ty, p->nz, p->batch)) * pp::kXWaves;
+// Partial records per batch entry written by an x kernel on this device
+// (<= p->nper, which sizes the partial region of the workspace); paired: the
+// inverse kernel with float spectra, which runs half the workgroups.
+int x_records(pp_plan p, bool paired) {
+    return pp::x_launch_grid(pp::x_blocks(p->ny, p->ty, p->nz, p->batch), paired) * pp::kXWaves;
 }
 
 template <typename T, typename Tio>
@@ -579,8 +580,8 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
     if ((st = mark(p, s, 0)) != PP_OK) return st;
     PP_HIP((pp::launch_xfwd<T, Tio>(f, S, partial, xa, p->batch, faces, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
-    PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
-                                    sc + pp::SC_MAXF, s));
+    PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p, false), p->batch, npts,
+                                    sc + pp::SC_COUNT + 3 * p->batch, sc + pp::SC_MAXF, s));
     if ((st = mark(p, s, 1)) != PP_OK) return st;
     PP_HIP(pp::launch_mid<T>(S, ma, p->batch, s));
     if ((st = mark(p, s, 2)) != PP_OK) return st;
@@ -627,7 +628,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     if ((st = mark(p, s, 0)) != PP_OK) return st;
     PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, faces, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
-    PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
+    PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p, false), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
                                     sc + pp::SC_MAXF, s));
     if ((st = mark(p, s, 1)) != PP_OK) return st;
     PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
@@ -635,7 +636,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     if ((st = mark(p, s, 2)) != PP_OK) return st;
     PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 0, s));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
-    PP_HIP(pp::launch_finalize_update(partial, x_records(p), p->batch, nregion, sc, 1, s));
+    PP_HIP(pp::launch_finalize_update(partial, x_records(p, true), p->batch, nregion, sc, 1, s));
     if ((st = mark(p, s, -1)) != PP_OK) return st;
     p->last_iters = 0;
     p->last_rel = 1.0;
@@ -645,13 +646,13 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         if ((st = mark(p, s, 0)) != PP_OK) return st;
         PP_HIP((pp::launch_xfwd<float, float>(r, S, partial, xa, p->batch, nullptr, s)));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
-        PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p), p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
+        PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p, false), p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
         if ((st = mark(p, s, 1)) != PP_OK) return st;
         PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
         if ((st = mark(p, s, 2)) != PP_OK) return st;
         PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 1, s));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
-        PP_HIP(pp::launch_finalize_update(partial, x_records(p), p->batch, nregion, sc, 0, s));
+        PP_HIP(pp::launch_finalize_update(partial, x_records(p, true), p->batch, nregion, sc, 0, s));
         if ((st = mark(p, s, -1)) != PP_OK) return st;
         double h[8];
         PP_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -142,6 +142,10 @@ struct ResidualArgs {
 // write one partial record per (batch entry, workgroup, wavefront).
 int x_blocks(int ny, int ty, int nz, int batch);
 int x_grid(int nblocks);
+// Grid of an x-kernel launch over nblocks row blocks: when the workgroups take
+// blocks in pairs (the inverse kernel with float spectra, x_next_block), half
+// as many are needed.
+int x_launch_grid(int nblocks, bool paired);
 
 // faces: null, or the face values to lift into the source as it is read.
 template <typename T, typename Tin>
