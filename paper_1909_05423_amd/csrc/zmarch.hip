@@ -316,14 +316,14 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 }
 
 // ---------------------------------------------------------------------------
-// Pipelined z march for y lines of up to NYMAX = 512 (both precisions) or
-// 1024 (float, whose chunk of 1024-long planes fits in LDS): the same stages as
-// k_zmarch, arranged so that the memory traffic of one chunk overlaps the
-// arithmetic of another.
+// Pipelined z march for y lines of up to NYMAX = 512 (NW = 8 wavefronts) or
+// 1024 (float: NW = 8; double: NW = 4, so that a chunk of 1024-long double
+// planes fits in LDS): the same stages as k_zmarch, arranged so that the
+// memory traffic of one chunk overlaps the arithmetic of another.
 //
-// A chunk is 8 planes, one per wavefront; a lane holds elements y = lane + 64 k
+// A chunk is NW planes, one per wavefront; a lane holds elements y = lane + 64 k
 // of its wavefront's plane, and a thread owns the z recurrences of entries
-// e = tid + 512 o (o < NYMAX / 512).  Upward, a lane prefetches its share of
+// e = tid + 64 NW o (o < OWN = NYMAX / (64 NW)).  Upward, a lane prefetches its share of
 // its wavefront's plane of the next chunk into registers while the current
 // chunk is transformed and eliminated; the pivots of the next chunk are
 // fetched after the current recurrences.  Downward, a thread prefetches its
@@ -335,13 +335,12 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 // memory operations, every wait retires only what it needs: at each point of
 // use, the operations issued after the awaited load are a fixed set (one
 // chunk's stores, or one chunk's prefetch).  FULL (ny == NYMAX, nz a multiple
-// of 8) removes every data-dependent branch around memory instructions, so the
+// of NW) removes every data-dependent branch around memory instructions, so the
 // compiler can count them exactly; barriers order LDS only.
-constexpr int kSZ = 8;        // planes per chunk = wavefronts per workgroup
-
-template <typename T, int NYMAX, bool FULL, bool PERZ>
-__global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
-    constexpr int NTH = 512;
+template <typename T, int NYMAX, int NW, bool FULL, bool PERZ>
+__global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
+    constexpr int NTH = 64 * NW;
+    constexpr int kSZ = NW;                      // planes per chunk = wavefronts per workgroup
     constexpr int EPL = NYMAX / 64;              // plane elements per lane
     constexpr int OWN = NYMAX / NTH;             // z-recurrence entries per thread
     constexpr int LDY = NYMAX + NYMAX / 8;       // work-buffer plane stride (>= padded_len(NYMAX))
@@ -410,7 +409,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
         if constexpr (PERZ) qnext[o] = a.qlast[(size_t)m * ny + ec[o]];
     }
 
-    // reciprocal pivots of planes zc .. zc+7 for the thread's entries (planes
+    // reciprocal pivots of planes zc .. zc+NW-1 for the thread's entries (planes
     // past the slot's rows read the first table element, which always exists;
     // the value then comes from winf / wlast); plane l, entry o at l * OWN + o
     cplx<T> pv[kSZ * OWN];
@@ -442,7 +441,7 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
             pre[k] = src[(FULL || y < ny) ? y : 0];
         }
     };
-    // downward prefetch: the thread's entries of planes zc .. zc+7 (clamped to the last plane)
+    // downward prefetch: the thread's entries of planes zc .. zc+NW-1 (clamped to the last plane)
     auto load_entry = [&](int zc) __attribute__((always_inline)) {
 #pragma unroll
         for (int l = 0; l < kSZ; ++l) {
@@ -683,17 +682,18 @@ __global__ __launch_bounds__(512) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
 }
 
-template <typename T, int NYMAX, bool FULL>
+template <typename T, int NYMAX, int NW, bool FULL>
 static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, NYMAX, FULL, true>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
-    else hipLaunchKernelGGL((k_zpipe<T, NYMAX, FULL, false>), dim3(a.slots, batch), dim3(512), 0, s, S, a);
+    const dim3 grid(a.slots, batch), block(64 * NW);
+    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, true>), grid, block, 0, s, S, a);
+    else hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false>), grid, block, 0, s, S, a);
     return hipGetLastError();
 }
 
-template <typename T, int NYMAX>
+template <typename T, int NYMAX, int NW>
 static hipError_t launch_pipe_any(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    if (a.ny == NYMAX && a.nz % kSZ == 0) return launch_pipe<T, NYMAX, true>(S, a, batch, s);
-    return launch_pipe<T, NYMAX, false>(S, a, batch, s);
+    if (a.ny == NYMAX && a.nz % NW == 0) return launch_pipe<T, NYMAX, NW, true>(S, a, batch, s);
+    return launch_pipe<T, NYMAX, NW, false>(S, a, batch, s);
 }
 
 template <typename T, int RMAX, int OWN>
@@ -709,17 +709,17 @@ static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, h
     return hipGetLastError();
 }
 
-// ny <= 512, and ny <= 1024 in float: the pipelined march; longer lines:
-// k_zmarch with 16 values per lane and two z entries per thread (ny <= 1024) or
-// 32 and 4 (ny <= 2048).
+// ny <= 1024: the pipelined march (8 wavefronts, or 4 for double lines over
+// 512); longer lines: k_zmarch with 32 values per lane and four z entries per
+// thread (ny <= 2048).
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     if (a.zsolver == 1) return launch_mid_pcr<T>(S, a, batch, s);
-    if (a.ny <= 512) return launch_pipe_any<T, 512>(S, a, batch, s);
-    if constexpr (sizeof(T) == 4) {
-        if (a.ny <= 1024) return launch_pipe_any<T, 1024>(S, a, batch, s);
+    if (a.ny <= 512) return launch_pipe_any<T, 512, 8>(S, a, batch, s);
+    if (a.ny <= 1024) {
+        if constexpr (sizeof(T) == 4) return launch_pipe_any<T, 1024, 8>(S, a, batch, s);
+        else return launch_pipe_any<T, 1024, 4>(S, a, batch, s);
     }
-    if (a.ny <= 1024) return launch_mid_shape<T, 16, 2>(S, a, batch, s);
     return launch_mid_shape<T, 32, 4>(S, a, batch, s);
 }
 

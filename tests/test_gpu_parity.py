@@ -204,27 +204,35 @@ def test_full_shapes(bc):
         assert rel_max(u, oracle.solve(f32, bc, h, "mean")) < 1e-5, ("f32", shape)
 
 
-# y lines of 513..1024 in float: the pipelined z march with two z entries per
-# thread (exact-count form at ny = 1024 with nz a multiple of 8; ragged nz;
-# 576 = 2^6 3^2 and 768 = 2^8 3 shorter than the line buffer).
-FLOAT_LONG_Y = [(16, 1024, 8), (13, 1024, 6), (9, 768, 4), (10, 576, 9), (24, 1024, 3)]
+# y lines of 513..1024: the pipelined z march with two z entries per thread in
+# float (8 wavefronts) and four in double (4 wavefronts, chunks of 4 planes);
+# exact-count forms at ny = 1024 with nz a multiple of 8; ragged nz; 576 = 2^6 3^2
+# and 768 = 2^8 3 shorter than the line buffer.
+LONG_Y = [(16, 1024, 8), (13, 1024, 6), (9, 768, 4), (10, 576, 9), (24, 1024, 3)]
 
 
 @pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDD", "NNDDND", "PPPPDD", "NNPPPP", "DDDDPP"])
-def test_float_long_y(bc):
+def test_long_y(bc):
     from gpu_util import banner, rel_max
     rng = np.random.default_rng(37 + sum(map(ord, bc)))
-    for shape in FLOAT_LONG_Y:
+    for shape in LONG_Y:
         h = tuple(1.0 / n for n in shape[::-1])
         f = rng.standard_normal(shape)
-        banner(f"float long y refined {bc} {shape}")
+        uo = oracle.solve(f, bc, h, "mean")
+        banner(f"long y f64 {bc} {shape}")
+        u, _ = _solve(f, bc, h)
+        assert rel_max(u, uo) < 1e-12, ("f64", shape)
+        banner(f"long y f64 adjoint {bc} {shape}")
+        v, _ = _solve(f, bc, h, adjoint=True)
+        assert rel_max(v, oracle.solve_adjoint(f, bc, h, "mean")) < 1e-12, ("f64 adjoint", shape)
+        banner(f"long y refined {bc} {shape}")
         u, plan = _solve(f, bc, h, dtype="f32_refined")
-        assert rel_max(u, oracle.solve(f, bc, h, "mean")) < 1e-12, ("refined", shape, plan.last_info())
+        assert rel_max(u, uo) < 1e-12, ("refined", shape, plan.last_info())
         f32 = f.astype(np.float32).astype(np.float64)
-        banner(f"float long y f32 {bc} {shape}")
+        banner(f"long y f32 {bc} {shape}")
         u, _ = _solve(f32, bc, h, dtype="f32")
         assert rel_max(u, oracle.solve(f32, bc, h, "mean")) < 1e-5, ("f32", shape)
-        banner(f"float long y adjoint {bc} {shape}")
+        banner(f"long y f32 adjoint {bc} {shape}")
         v, _ = _solve(f32, bc, h, dtype="f32", adjoint=True)
         assert rel_max(v, oracle.solve_adjoint(f32, bc, h, "mean")) < 1e-5, ("adjoint", shape)
 
