@@ -822,7 +822,13 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         // LDS: the lines plus two twiddle tables of nx; fewer lines to keep two
         // workgroups per CU, and a single line may use the whole LDS
         auto xlds = [&](int l) { return ((size_t)l * pp::padded_len(nx) + 2 * (size_t)nx) * p->elem; };
+        const int lines_all = lines;
         while (lines > 1 && xlds(lines) > (size_t)pp::kXLdsBytes) --lines;
+        // except for the exact-count shape (one line of 64 rmax values per
+        // wavefront, kXWaves lines): kept at one workgroup per CU when its LDS
+        // allows (double rows of 1024), since the general form is slower still
+        if (lines_all == pp::kXWaves && lpw == 1 && nx == 64 * pp::xdir_rmax(nx) && xlds(lines_all) <= (size_t)pp::kXLdsMax)
+            lines = lines_all;
         if (xlds(lines) > (size_t)pp::kXLdsMax) lines = 0;
     }
     // z planes per chunk: each wavefront of the z march transforms whole planes,
