@@ -658,6 +658,8 @@ static hipError_t launch_xfwd_shape(const Tin* f, cplx<T>* S, double* partial, c
 template <typename T, typename Tin, bool FACES>
 static hipError_t launch_xfwd_any(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
                                   const FaceArgs<Tin>& fa, hipStream_t s) {
+    // rows of 384 = 64 x 6: exact-count form with six values per lane
+    if (a.nx == 384) return launch_xfwd_shape<T, Tin, 6, FACES>(f, S, partial, a, batch, fa, s);
     if (a.nx <= 512) return launch_xfwd_shape<T, Tin, 8, FACES>(f, S, partial, a, batch, fa, s);
     if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, 16, FACES>(f, S, partial, a, batch, fa, s);
     return launch_xfwd_shape<T, Tin, 32, FACES>(f, S, partial, a, batch, fa, s);
@@ -694,6 +696,8 @@ static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const XArgs<T>& a
 template <typename T, typename Tout, int MODE>
 static hipError_t launch_xinv_any(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
                                   const double* scalars, int gauge_region, double* partial, hipStream_t s) {
+    if (a.nx == 384)   // 64 x 6: exact-count form with six values per lane
+        return launch_xinv_shape<T, Tout, MODE, 6>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx <= 512)
         return launch_xinv_shape<T, Tout, MODE, 8>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx <= 1024)

@@ -181,7 +181,8 @@ def test_mms_ppd_workload_small():
 # the oracle's own double-precision error (about eps times the condition
 # number) to exceed 1e-12; on the unit cube it stays below 1e-13 for every
 # shape and boundary set here (checked with a long-double residual correction).
-FULL_SHAPES = [(8, 8, 512), (16, 512, 16), (8, 16, 1024), (16, 512, 512), (9, 8, 512), (13, 512, 12), (8, 12, 512)]
+FULL_SHAPES = [(8, 8, 512), (16, 512, 16), (8, 16, 1024), (16, 512, 512), (9, 8, 512), (13, 512, 12), (8, 12, 512),
+               (8, 16, 384), (6, 12, 384)]
 
 
 @pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDD", "NNDDND", "PPPPDD"])
