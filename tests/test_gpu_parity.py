@@ -182,7 +182,7 @@ def test_mms_ppd_workload_small():
 # number) to exceed 1e-12; on the unit cube it stays below 1e-13 for every
 # shape and boundary set here (checked with a long-double residual correction).
 FULL_SHAPES = [(8, 8, 512), (16, 512, 16), (8, 16, 1024), (16, 512, 512), (9, 8, 512), (13, 512, 12), (8, 12, 512),
-               (8, 16, 384), (6, 12, 384)]
+               (8, 16, 384), (6, 12, 384), (12, 384, 8), (7, 384, 6)]
 
 
 @pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDD", "NNDDND", "PPPPDD"])

@@ -80,7 +80,8 @@ def test_periodic_z_gauges_and_adjoint(bc, gauge):
 
 
 # the exact-count forms and the long-line form of the z march, on the unit cube
-FULL_SHAPES = [(16, 512, 16), (8, 8, 512), (16, 512, 512), (9, 512, 12), (4, 1024, 4), (3, 2048, 2)]
+FULL_SHAPES = [(16, 512, 16), (8, 8, 512), (16, 512, 512), (9, 512, 12), (4, 1024, 4), (3, 2048, 2), (12, 384, 8),
+               (7, 384, 6), (8, 1024, 4)]
 
 
 @pytest.mark.parametrize("bc", ["PPPPPP", "DDNNPP", "NNPPPP"])
