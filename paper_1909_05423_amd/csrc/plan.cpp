@@ -44,6 +44,7 @@ struct pp_plan_s {
     // tables (uploaded into the workspace)
     std::vector<unsigned char> blob;
     size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
+    size_t t_elen = 0;
     size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
     int zsolver = 0;     // 0 Thomas (fused march), 1 PCR
     // periodic z (Sherman-Morrison)
@@ -310,7 +311,7 @@ template <typename T> void build_tables(pp_plan p) {
     };
 
     const int slots = p->slots;
-    std::vector<int> rowoff(slots), lmax(slots);
+    std::vector<int> rowoff(slots), lmax(slots), elen((size_t)slots * ny);
     std::vector<T> winf((size_t)slots * ny * 2), wlast((size_t)slots * ny * 2);
     std::vector<std::vector<Line<T>>> lines(slots);
     size_t rows = 0;
@@ -342,6 +343,8 @@ template <typename T> void build_tables(pp_plan p) {
                 winf[((size_t)m * ny + e) * 2 + part] = ln.winf;
                 wlast[((size_t)m * ny + e) * 2 + part] = ln.wlast;
                 lm = std::max(lm, ln.tail);
+                int& el = elen[(size_t)m * ny + e];
+                el = part ? std::max(el, ln.tail) : ln.tail;
             }
         }
         rowoff[m] = (int)rows;
@@ -353,6 +356,11 @@ template <typename T> void build_tables(pp_plan p) {
     std::memcpy(p->blob.data() + p->t_rowoff, rowoff.data(), sizeof(int) * slots);
     p->t_lmax = em.put(sizeof(int) * slots);
     std::memcpy(p->blob.data() + p->t_lmax, lmax.data(), sizeof(int) * slots);
+    // per-entry lengths: a lane reads its table row only while its entry's
+    // pivots still change, so slots with a few slowly converging entries (the
+    // smallest wavenumbers) do not read whole rows for most of z
+    p->t_elen = em.put(sizeof(int) * elen.size());
+    std::memcpy(p->blob.data() + p->t_elen, elen.data(), sizeof(int) * elen.size());
     p->t_winf = em.put(sizeof(T) * winf.size());
     std::memcpy(p->blob.data() + p->t_winf, winf.data(), sizeof(T) * winf.size());
     p->t_wlast = em.put(sizeof(T) * wlast.size());
@@ -498,6 +506,7 @@ template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, 
     a.mky = reinterpret_cast<const cplx<T>*>(t + p->t_mky);
     a.rowoff = reinterpret_cast<const int*>(t + p->t_rowoff);
     a.lmax = reinterpret_cast<const int*>(t + p->t_lmax);
+    a.elen = reinterpret_cast<const int*>(t + p->t_elen);
     a.wrows = reinterpret_cast<const cplx<T>*>(t + p->t_wrows);
     a.winf = reinterpret_cast<const cplx<T>*>(t + p->t_winf);
     a.wlast = reinterpret_cast<const cplx<T>*>(t + p->t_wlast);

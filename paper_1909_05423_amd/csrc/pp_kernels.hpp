@@ -107,6 +107,7 @@ template <typename T> struct MidArgs {
     const cplx<T>* mky;      // exp(-i pi k / (2 ny))
     const int* rowoff;       // per slot: first table row
     const int* lmax;         // per slot: rows stored (z < lmax reads the table)
+    const int* elen;         // per (slot, entry): rows in which this entry's pivots differ from winf (<= lmax)
     const cplx<T>* wrows;    // [row][ny] (w_re, w_im) reciprocal pivots
     const cplx<T>* winf;     // [slot][ny] converged reciprocal pivot
     const cplx<T>* wlast;    // [slot][ny] reciprocal pivot of the last row

@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
     const bool sing = a.singular && (m == 0);
-    const int lmax = a.lmax[m], roff = a.rowoff[m];
+    const int roff = a.rowoff[m];
     const T scale = a.scale;
     const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
     const int half = (ny >> 1) + 1;
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     const int last = (nchunks - 1) * kSZ;
 
     // this thread's z-recurrence entries (entries past ny read a valid dummy)
-    int ec[OWN];
+    int ec[OWN], elen[OWN];
     bool live[OWN];
     cplx<T> winf[OWN], wlast[OWN];
     // periodic z: y_0 accumulated on the way up, the correction c = (y_0 +
@@ -402,6 +402,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
         live[o] = FULL || e < ny;
         ec[o] = live[o] ? e : 0;
         winf[o] = a.winf[(size_t)m * ny + ec[o]];
+        elen[o] = a.elen[(size_t)m * ny + ec[o]];
         wlast[o] = a.wlast[(size_t)m * ny + ec[o]];
         y0[o] = mk<T>(T(0), T(0));
         corr[o] = y0[o];
@@ -410,8 +411,9 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     }
 
     // reciprocal pivots of planes zc .. zc+NW-1 for the thread's entries (planes
-    // past the slot's rows read the first table element, which always exists;
-    // the value then comes from winf / wlast); plane l, entry o at l * OWN + o
+    // past the entry's own rows read the first table element, which always
+    // exists; the value then comes from winf / wlast); plane l, entry o at
+    // l * OWN + o
     cplx<T> pv[kSZ * OWN];
     auto load_piv = [&](int zc) __attribute__((always_inline)) {
 #pragma unroll
@@ -419,8 +421,8 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
             const int z = zc + l;
 #pragma unroll
             for (int o = 0; o < OWN; ++o) {
-                // past the slot's rows every lane reads the same element, one cache line per wavefront
-                const cplx<T>* src = (z < lmax) ? a.wrows + (size_t)(roff + z) * ny + ec[o] : a.wrows;
+                // lanes past their entry's rows read the same element (one cache line)
+                const cplx<T>* src = (z < elen[o]) ? a.wrows + (size_t)(roff + z) * ny + ec[o] : a.wrows;
                 pv[l * OWN + o] = *src;
             }
         }
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     // (component-wise selects between values, so that the arrays stay in registers)
     auto pivot = [&](int z, int l, int o) __attribute__((always_inline)) -> cplx<T> {
         const cplx<T> p = pv[l * OWN + o], wi = winf[o], wl = wlast[o];
-        const bool lastrow = (z == nz - 1), tab = (z < lmax);
+        const bool lastrow = (z == nz - 1), tab = (z < elen[o]);
         return mk<T>(lastrow ? wl.x : (tab ? p.x : wi.x), lastrow ? wl.y : (tab ? p.y : wi.y));
     };
     // upward prefetch: elements y = lane + 64 k of plane zc + wave (clamped to the last plane)
