@@ -48,6 +48,7 @@ struct pp_plan_s {
     size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
     int zsolver = 0;     // 0 Thomas (fused march), 1 PCR
     // periodic z (Sherman-Morrison)
+    size_t t_aelen = 0, t_qelen = 0;
     size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
            t_invgam = 0;
     size_t table_rows = 0;
@@ -403,8 +404,14 @@ template <typename T> void build_tables(pp_plan p) {
     }
     if (p->bz0 != pp::BC_P) return;
     // periodic z: Sherman-Morrison rows (alpha, qp) per slot, and per-entry scalars
-    auto emit_rows = [&](std::vector<T> Line<T>::*vec, size_t* t_off, size_t* t_len, size_t* t_rows) {
-        std::vector<int> off(slots), len(slots);
+    auto emit_rows = [&](std::vector<T> Line<T>::*vec, size_t* t_off, size_t* t_len, size_t* t_rows, size_t* t_elen) {
+        std::vector<int> off(slots), len(slots), elen((size_t)slots * ny);
+        for (int m = 0; m < slots; ++m)
+            for (int e = 0; e < ny; ++e)
+                elen[(size_t)m * ny + e] = (int)std::max((lines[m][(size_t)e * 2].*vec).size(),
+                                                         (lines[m][(size_t)e * 2 + 1].*vec).size());
+        *t_elen = em.put(sizeof(int) * elen.size());
+        std::memcpy(p->blob.data() + *t_elen, elen.data(), sizeof(int) * elen.size());
         size_t nrows = 0;
         for (int m = 0; m < slots; ++m) {
             int L = 0;
@@ -427,8 +434,8 @@ template <typename T> void build_tables(pp_plan p) {
                         rr[((size_t)(off[m] + z) * ny + e) * 2 + part] = (z < (int)v.size()) ? v[z] : T(0);
                     }
     };
-    emit_rows(&Line<T>::alpha, &p->t_aoff, &p->t_alen, &p->t_arows);
-    emit_rows(&Line<T>::qp, &p->t_qoff, &p->t_qlen, &p->t_qrows);
+    emit_rows(&Line<T>::alpha, &p->t_aoff, &p->t_alen, &p->t_arows, &p->t_aelen);
+    emit_rows(&Line<T>::qp, &p->t_qoff, &p->t_qlen, &p->t_qrows, &p->t_qelen);
     auto emit_scalar = [&](T Line<T>::*field, size_t* t) {
         *t = em.put(sizeof(T) * 2 * (size_t)slots * ny);
         T* v = reinterpret_cast<T*>(p->blob.data() + *t);
@@ -518,6 +525,8 @@ template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, 
     if (a.zper) {
         a.aoff = reinterpret_cast<const int*>(t + p->t_aoff);
         a.alen = reinterpret_cast<const int*>(t + p->t_alen);
+        a.aelen = reinterpret_cast<const int*>(t + p->t_aelen);
+        a.qelen = reinterpret_cast<const int*>(t + p->t_qelen);
         a.arows = reinterpret_cast<const cplx<T>*>(t + p->t_arows);
         a.qoff = reinterpret_cast<const int*>(t + p->t_qoff);
         a.qlen = reinterpret_cast<const int*>(t + p->t_qlen);

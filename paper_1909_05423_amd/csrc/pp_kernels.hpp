@@ -116,6 +116,7 @@ template <typename T> struct MidArgs {
     // forward-eliminated rank-one vector; per entry its last value, 1/den, 1/gamma
     int zper;
     const int *aoff, *alen, *qoff, *qlen;
+    const int *aelen, *qelen;   // per (slot, entry): rows of alpha / qp before they are zero
     const cplx<T> *arows, *qrows, *qlast, *inv_den, *inv_gamma;
     // z solver: 0 = fused Thomas march, 1 = parallel cyclic reduction (separate y passes)
     int zsolver;

@@ -388,12 +388,13 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     // periodic z: y_0 accumulated on the way up, the correction c = (y_0 +
     // y_{n-1}/gamma)/den at the turn, and q_z rebuilt on the way down (the
     // Sherman-Morrison rows decay from z = 0, so only the first chunks read them)
+    // (rows per entry: ael / qel; their maximum over the wavefront: alw / qlw,
+    // so whole wavefronts skip the rows once their entries' values are zero)
     cplx<T> y0[OWN], corr[OWN], qnext[OWN];
-    int alen = 0, aoff = 0, qlen = 0, qoff = 0;
+    int aoff = 0, qoff = 0;
+    int ael[OWN], qel[OWN], alw[OWN], qlw[OWN];
     if constexpr (PERZ) {
-        alen = a.alen[m];
         aoff = a.aoff[m];
-        qlen = a.qlen[m];
         qoff = a.qoff[m];
     }
 #pragma unroll
@@ -407,7 +408,19 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
         y0[o] = mk<T>(T(0), T(0));
         corr[o] = y0[o];
         qnext[o] = y0[o];
-        if constexpr (PERZ) qnext[o] = a.qlast[(size_t)m * ny + ec[o]];
+        if constexpr (PERZ) {
+            qnext[o] = a.qlast[(size_t)m * ny + ec[o]];
+            ael[o] = live[o] ? a.aelen[(size_t)m * ny + ec[o]] : 0;
+            qel[o] = live[o] ? a.qelen[(size_t)m * ny + ec[o]] : 0;
+            int x = ael[o], y = qel[o];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                x = max(x, __shfl_xor(x, off, 64));
+                y = max(y, __shfl_xor(y, off, 64));
+            }
+            alw[o] = __builtin_amdgcn_readfirstlane(x);
+            qlw[o] = __builtin_amdgcn_readfirstlane(y);
+        }
     }
 
     // reciprocal pivots of planes zc .. zc+NW-1 for the thread's entries (planes
@@ -537,10 +550,10 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
             const int e = ec[o];
             cplx<T> al[PERZ ? kSZ : 1];
             if constexpr (PERZ) {
-                if (zc < alen) {
+                if (zc < alw[o]) {
 #pragma unroll
                     for (int l = 0; l < kSZ; ++l)
-                        al[l] = (zc + l < alen) ? a.arows[(size_t)(aoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
+                        al[l] = (zc + l < ael[o]) ? a.arows[(size_t)(aoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
                 }
             }
             cplx<T> prev = st[o];
@@ -552,7 +565,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
                     cplx<T> d = cscale(work[l * LDY + pad(e)], scale);
                     if (sing && e == 0) d.x -= proj;
                     if constexpr (PERZ) {
-                        if (zc < alen) {
+                        if (zc < alw[o]) {
                             y0[o].x += al[l].x * d.x;
                             y0[o].y += al[l].y * d.y;
                         }
@@ -595,10 +608,10 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
             const int e = ec[o];
             cplx<T> qv[PERZ ? kSZ : 1];
             if constexpr (PERZ) {
-                if (zc < qlen) {
+                if (zc < qlw[o]) {
 #pragma unroll
                     for (int l = 0; l < kSZ; ++l)
-                        qv[l] = (zc + l < qlen) ? a.qrows[(size_t)(qoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
+                        qv[l] = (zc + l < qel[o]) ? a.qrows[(size_t)(qoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
                 }
             }
             cplx<T> nxt = st[o];
@@ -614,7 +627,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
                     if constexpr (PERZ) {
                         // q_z of the rank-one vector, then u_z = y_z - c q_z
                         if (z != nz - 1) {
-                            const cplx<T> qp = (zc < qlen) ? qv[l] : mk<T>(T(0), T(0));
+                            const cplx<T> qp = (zc < qlw[o]) ? qv[l] : mk<T>(T(0), T(0));
                             qnext[o] = mk<T>(qp.x - w.x * qnext[o].x, qp.y - w.y * qnext[o].y);
                         }
                         un = mk<T>(nxt.x - corr[o].x * qnext[o].x, nxt.y - corr[o].y * qnext[o].y);
