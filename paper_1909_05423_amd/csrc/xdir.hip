@@ -105,14 +105,15 @@ template <typename T> __device__ __forceinline__ void put_spec(cplx<T>* p, const
 // Minimum waves per SIMD the compiler must leave room for.  2 for the
 // all-float forward kernel (on rows of 1024 it would otherwise take every
 // register and run one wave per SIMD; measured 1.64 -> 1.21 ms at
-// 1024 x 1024 x 512) and for the double kernel on rows of 512 (4 registers
-// over the budget of two waves); no constraint elsewhere (the other kernels
-// with double data spill under it).
-template <typename T, typename Tin, int RMAX>
-constexpr int kXfwdMinWaves = ((sizeof(T) == 4 && sizeof(Tin) == 4) || (sizeof(T) == 8 && RMAX == 8)) ? 2 : 1;
+// 1024 x 1024 x 512) and for the double kernel on rows of 512 without face
+// values (4 registers over the budget of two waves); no constraint elsewhere
+// (the other kernels with double data spill under it).
+template <typename T, typename Tin, int RMAX, bool FACES>
+constexpr int kXfwdMinWaves =
+    ((sizeof(T) == 4 && sizeof(Tin) == 4) || (sizeof(T) == 8 && RMAX == 8 && !FACES)) ? 2 : 1;
 
 template <typename T, typename Tin, int NTH, int RMAX, bool FULL, bool FACES>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWaves<T, Tin, RMAX>))) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWaves<T, Tin, RMAX, FACES>))) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
                                               double* __restrict__ partial, XArgs<T> a, int nblocks,
                                               FaceArgs<Tin> fa) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -133,10 +134,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
     }
     const int epl = FULL ? RMAX : (nx + 63) >> 6;
     const float inv_epl = 1.0f / (float)epl, inv_nl = 1.0f / (float)nlines;
-    // periodic rows of 512 without face values, double spectra: the
-    // transform's first stage runs on the row registers (w512_first; in float
-    // the extra registers cost more occupancy than the LDS round trip saves)
-    constexpr bool R512 = FULL && RMAX == 8 && !FACES && sizeof(T) == 8;
+    // periodic rows of 512, double spectra: the transform's first stage runs
+    // on the row registers (w512_first; in float the extra registers cost more
+    // occupancy than the LDS round trip saves)
+    constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8;
     const bool reg512 = R512 && a.bx == BC_P;
 
     // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
@@ -265,10 +266,31 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
             }
         }
         // the remaining face lifts, applied to the lines in place: y and z faces
-        // (boundary rows and planes only; FULL) or every face (general form)
+        // (boundary rows and planes only; FULL) or every face (general form).
+        // On the w512 path the line is still in registers (a loop of its own:
+        // one shared with the LDS form would make the compiler choose between a
+        // register and an LDS address, which moves the registers to memory)
+        if constexpr (FACES && R512) {
+            if (reg512) {
+                const int ya = xb.y0 + 2 * wave;
+                if (ya == 0 || ya + 1 == ny - 1 || xb.z == 0 || xb.z == nz - 1) {
+#pragma unroll
+                    for (int r = 0; r < RMAX; ++r) {
+                        const int n = lane + 64 * r;
+                        const double la = face_lift_yz(fa, xb.b, n, ya, xb.z, nx, ny, nz);
+                        const double lb = face_lift_yz(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
+                        const double fa_ = (double)vf[r].x - la, fb_ = (double)vf[r].y - lb;
+                        acc -= la + lb;
+                        amax = fmax(amax, fmax(fabs(fa_), fabs(fb_)));
+                        vf[r] = mk<T>((T)fa_, (T)fb_);
+                    }
+                }
+            }
+        }
         if constexpr (FACES) {
 #pragma unroll
             for (int r = 0; r < RMAX; ++r) {
+                if (reg512) break;
                 const int p = FULL ? 0 : fdiv(r, inv_epl);
                 const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
                 const int ya = xb.y0 + 2 * j;
