@@ -122,6 +122,31 @@ def test_batched_equals_single():
             np.testing.assert_allclose(means, f.mean(axis=(1, 2, 3)), atol=1e-14)
 
 
+# batch entries through the exact-count kernel forms (x rows of 384 / 512 /
+# 1024, y lines of 384 / 512 / 1024)
+BATCH_FULL_SHAPES = [(8, 16, 512), (8, 512, 16), (8, 8, 1024), (8, 1024, 4), (12, 16, 384), (12, 384, 8)]
+
+
+@pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDD"])
+def test_batched_full_shapes(bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(23 + sum(map(ord, bc)))
+    for shape in BATCH_FULL_SHAPES:
+        h = tuple(1.0 / n for n in shape[::-1])
+        f = rng.standard_normal((2,) + shape) + np.array([0.3, -0.2])[:, None, None, None]
+        uo = [oracle.solve(f[b], bc, h, "mean") for b in range(2)]
+        for dtype in ("f64", "f32_refined"):
+            banner(f"batched {dtype} {bc} {shape}")
+            ub, plan = _solve(f, bc, h, dtype=dtype, batch=2)
+            for b in range(2):
+                assert rel_max(ub[b], uo[b]) < 1e-12, (dtype, shape, b)
+        banner(f"batched f32 {bc} {shape}")
+        f32 = f.astype(np.float32).astype(np.float64)
+        ub, _ = _solve(f32, bc, h, dtype="f32", batch=2)
+        for b in range(2):
+            assert rel_max(ub[b], oracle.solve(f32[b], bc, h, "mean")) < 1e-5, ("f32", shape, b)
+
+
 def test_nonfinite_source_reported():
     import torch
     from paper_1909_05423_amd import Plan, _lib
