@@ -28,10 +28,12 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpts/s per solve at 512^3 (FP64 vs FP32+refine @1e-12); % peak HBM BW"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published peak
 GROUPS = ("x_forward", "z_march", "x_inverse", "other")
-KERNEL_NAMES = {"x_forward": "k_xfwd", "z_march": "k_zpipe", "x_inverse": "k_xinv"}   # k_zmarch when ny > 512
+KERNEL_NAMES = {"x_forward": "k_xfwd", "z_march": "k_zpipe", "x_inverse": "k_xinv"}   # k_zmarch when ny > 1024
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+# sources whose changes can change the kernels' traffic (the plan code lays out
+# the tables the z march reads)
 SOURCES = [os.path.join(ROOT, "paper_1909_05423_amd", "csrc", n)
-           for n in ("pp_device.hpp", "pp_kernels.hpp", "xdir.hip", "zmarch.hip", "zpcr.hip")]
+           for n in ("pp_device.hpp", "pp_kernels.hpp", "xdir.hip", "zmarch.hip", "zpcr.hip", "plan.cpp")]
 
 
 def log(msg):
@@ -112,7 +114,7 @@ def roofline_block(per, abytes, workload, dtype, ny):
     achieved = abytes[best] / (k["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_for(best, workload, dtype)
     name = KERNEL_NAMES[best]
-    if best == "z_march" and ny > 512:
+    if best == "z_march" and ny > 1024:
         name = "k_zmarch"
     return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
                 unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
