@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--skip-refined", action="store_true")
     ap.add_argument("--skip-faces", action="store_true", help="skip timing the solve with face values")
     ap.add_argument("--skip-periodic-z", action="store_true", help="skip timing the periodic-z solve")
-    ap.add_argument("--skip-pcr", action="store_true", help="skip timing the PCR z solver")
+    ap.add_argument("--skip-pcr", action="store_true", help="skip timing the PCR and CR-P z solvers")
     ap.add_argument("--skip-check", action="store_true", help="skip the host-side backward-error check")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) three times, as the reference "
@@ -297,18 +297,20 @@ def main():
         del plan_p, up
 
     if not args.skip_pcr and shape[0] <= 512 and shape[1] <= 512 and bc[4:6] != "PP":
-        # the same solve with the z-systems by parallel cyclic reduction (y
-        # transforms as separate passes), for comparison with the fused march
-        plan_c = Plan(shape, bc, h, dtype="f64", batch=batch, zsolver="pcr")
-        uc = torch.empty_like(f)
-        ms_c, _, per_c = time_solves(plan_c, f, uc, args.steps, args.warmup, lib)
-        result["pcr"] = {
-            "value": round(npts / ms_c / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_c, 4),
-            "max_rel_diff_vs_thomas": float((uc - u).abs().max() / u.abs().max()),
-            "kernels": {g: dict(per_c[g]) for g in GROUPS},
-        }
-        log(f"f64 with PCR z solver: {ms_c:.3f} ms/solve")
-        del plan_c, uc
+        # the same solve with the z-systems by parallel cyclic reduction and by
+        # cyclic reduction (y transforms as separate passes), for comparison
+        # with the fused march
+        for key in ("pcr", "cr"):
+            plan_c = Plan(shape, bc, h, dtype="f64", batch=batch, zsolver=key)
+            uc = torch.empty_like(f)
+            ms_c, _, per_c = time_solves(plan_c, f, uc, args.steps, args.warmup, lib)
+            result[key] = {
+                "value": round(npts / ms_c / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_c, 4),
+                "max_rel_diff_vs_thomas": float((uc - u).abs().max() / u.abs().max()),
+                "kernels": {g: dict(per_c[g]) for g in GROUPS},
+            }
+            log(f"f64 with {key.upper()} z solver: {ms_c:.3f} ms/solve")
+            del plan_c, uc
 
     if not args.skip_refined:
         plan_r = Plan(shape, bc, h, dtype="f32_refined", batch=batch)

@@ -94,14 +94,16 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
 pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
 
 /* z solver (sections "Solution of the Resulting Tridiagonal Matrices",
- * "Parallel Cyclic Reduction").
+ * "Cyclic Reduction Technique", "Parallel Cyclic Reduction").
  *   PP_ZSOLVER_THOMAS  default: Thomas, fused with the y transforms in one
  *                      march along z (two passes over the spectral array).
  *   PP_ZSOLVER_PCR     parallel cyclic reduction on whole z lines in LDS, with
  *                      the y transforms as separate passes (four passes);
- *                      nz <= 512 and ny <= 512 (PP_ERR_SIZE otherwise), z not
- *                      periodic (PP_ERR_BC).  For comparison with the default. */
-typedef enum { PP_ZSOLVER_THOMAS = 0, PP_ZSOLVER_PCR = 1 } pp_zsolver;
+ *   PP_ZSOLVER_CR      cyclic reduction with a parallel backward phase (CR-P),
+ *                      arranged like PCR.
+ *   PCR and CR-P: nz <= 512 and ny <= 512 (PP_ERR_SIZE otherwise), z not
+ *   periodic (PP_ERR_BC).  For comparison with the default. */
+typedef enum { PP_ZSOLVER_THOMAS = 0, PP_ZSOLVER_PCR = 1, PP_ZSOLVER_CR = 2 } pp_zsolver;
 pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
 
 /* Refinement controls for PP_F32_REFINED: stop once the estimated relative

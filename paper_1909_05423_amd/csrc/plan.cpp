@@ -46,7 +46,7 @@ struct pp_plan_s {
     size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
     size_t t_elen = 0;
     size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
-    int zsolver = 0;     // 0 Thomas (fused march), 1 PCR
+    int zsolver = 0;     // 0 Thomas (fused march), 1 PCR, 2 CR-P
     // periodic z (Sherman-Morrison)
     size_t t_aelen = 0, t_qelen = 0;
     size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
@@ -895,8 +895,8 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge) {
 }
 
 pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver) {
-    if (!p || (solver != PP_ZSOLVER_THOMAS && solver != PP_ZSOLVER_PCR)) return PP_ERR_ARG;
-    if (solver == PP_ZSOLVER_PCR) {
+    if (!p || (solver != PP_ZSOLVER_THOMAS && solver != PP_ZSOLVER_PCR && solver != PP_ZSOLVER_CR)) return PP_ERR_ARG;
+    if (solver == PP_ZSOLVER_PCR || solver == PP_ZSOLVER_CR) {
         if (p->bz0 == pp::BC_P) return PP_ERR_BC;
         if (p->nz > 512 || p->ny > 512) return PP_ERR_SIZE;
     }

@@ -118,7 +118,7 @@ template <typename T> struct MidArgs {
     const int *aoff, *alen, *qoff, *qlen;
     const int *aelen, *qelen;   // per (slot, entry): rows of alpha / qp before they are zero
     const cplx<T> *arows, *qrows, *qlast, *inv_den, *inv_gamma;
-    // z solver: 0 = fused Thomas march, 1 = parallel cyclic reduction (separate y passes)
+    // z solver: 0 = fused Thomas march, 1 = parallel cyclic reduction, 2 = CR-P (separate y passes)
     int zsolver;
     int bz0, bz1;            // z face types (Bc) of the end rows
     const cplx<T>* bmid;     // [slot][ny] interior diagonal hz^2 lam - 2 of each part's z-system
@@ -171,7 +171,7 @@ hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s)
 // The same stage with the z-systems solved by parallel cyclic reduction
 // (y transforms as separate passes; nz <= 512, ny <= 512, z not periodic).
 template <typename T>
-hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);
+hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s, bool cr);
 
 // Finalise the x-forward partials: mu[b] = sum / npts, scalars[SC_MAXF] = max |f|.
 hipError_t launch_finalize_xfwd(const double* partial, int nper, int batch, double npts, double* mu,

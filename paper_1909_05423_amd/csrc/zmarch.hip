@@ -729,7 +729,7 @@ static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, h
 // four z entries per thread (ny <= 2048).
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    if (a.zsolver == 1) return launch_mid_pcr<T>(S, a, batch, s);
+    if (a.zsolver == 1 || a.zsolver == 2) return launch_mid_pcr<T>(S, a, batch, s, a.zsolver == 2);
     // float lines of 384: one entry per thread, no idle lanes (measured 1.42 ->
     // 1.12 ms at 384^3 x 4; in double the 8-wavefront form is as fast)
     if constexpr (sizeof(T) == 4) {

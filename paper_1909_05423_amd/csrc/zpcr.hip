@@ -1,13 +1,15 @@
-// Alternative z solver: parallel cyclic reduction (section "Parallel Cyclic
-// Reduction").  Selected per plan; the default is the fused Thomas march.
+// Alternative z solvers: parallel cyclic reduction (section "Parallel Cyclic
+// Reduction") and cyclic reduction with a parallel backward phase (section
+// "Cyclic Reduction Technique", CR-P).  Selected per plan; the default is the
+// fused Thomas march.
 //
-// PCR needs a whole z line of a mode on chip at once, while the y transform
+// Both need a whole z line of a mode on chip at once, while the y transform
 // needs a whole y line of a plane, so this path runs them as separate passes
 // over the spectral array S:
-//   k_ypass<FWD>   y transform of every (slot, plane), in place;
-//   k_zpcr         PCR along z for tiles of TE entries of one slot, the whole
-//                  line of each entry in LDS;
-//   k_ypass<INV>   inverse y transform, in place.
+//   k_ypass<FWD>     y transform of every (slot, plane), in place;
+//   k_zpcr / k_zcr   PCR / CR-P along z for tiles of TE entries of one slot,
+//                    the whole line of each entry in LDS;
+//   k_ypass<INV>     inverse y transform, in place.
 // Two more HBM sweeps than the fused march (the point of the comparison).
 //
 // PCR on the normalised system (diagonal 1): row j reads
@@ -121,39 +123,33 @@ __global__ __launch_bounds__(512) void k_ypass(cplx<T>* __restrict__ S, MidArgs<
     }
 }
 
-// ---------------------------------------------------------------- PCR along z
+// ------------------------------------------------ PCR and CR-P along z
 // TE entries of one slot per 256-thread workgroup; LDS holds, per (entry, z),
 // the right-hand side x (complex: the real and imaginary parts are separate
-// systems) and the two off-diagonals of each part.  The reduction runs in
-// double for either solve precision: its log2(nz) levels of combined rows lose
-// more to rounding than the Thomas recurrence does, which in float exceeds the
-// unrefined float tolerance on long lines.
+// systems) and the two off-diagonals of each part.  The reductions run in
+// double for either solve precision: their log2(nz) levels of combined rows
+// lose more to rounding than the Thomas recurrence does, which in float
+// exceeds the unrefined float tolerance on long lines.
 constexpr int kPcrThreads = 256;
 template <typename T> constexpr int pcr_te() { return 4; }
 template <typename T> constexpr size_t pcr_lds_bytes(int nz) {
     return (size_t)pcr_te<T>() * nz * (sizeof(double2) + 4 * sizeof(double)) + 64 * sizeof(double);
 }
 
-template <typename Tio>
-__global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a) {
+// Load TE z lines of slot m into LDS (rows r = z * TE + el), scaled and
+// normalised to a unit diagonal; the zero mode pinned (row 0: u_0 = 0, row 1
+// without its coupling to u_0).  X[r] = right-hand side, AC[r] = (a.x, a.y,
+// c.x, c.y): lower and upper off-diagonals of the two parts.
+template <typename Tio, int TE>
+__device__ void tri_load(const cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int e0,
+                         cplx<double>* X, double* AC) {
     using T = double;
-    constexpr int TE = pcr_te<Tio>();
-    constexpr int ITEMS = 512 * TE / kPcrThreads;   // (entry, z) rows per thread at nz = 512
-    extern __shared__ __align__(16) unsigned char smem[];
     const int nz = a.nz, ny = a.ny;
-    const int m = blockIdx.y, b = blockIdx.z;
-    const int e0 = blockIdx.x * TE;
-    const int tid = threadIdx.x;
-    cplx<T>* X = reinterpret_cast<cplx<T>*>(smem);            // [z][TE]
-    T* AC = reinterpret_cast<T*>(X + (size_t)nz * TE);         // [z][TE][4]: a.x, a.y, c.x, c.y
-    double* red = reinterpret_cast<double*>(AC + (size_t)nz * TE * 4);
-    const size_t base = (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride;
     const bool sing = a.singular && m == 0;
     const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
     const T d0 = (a.bz0 == BC_D) ? T(-1) : T(1), d1 = (a.bz1 == BC_D) ? T(-1) : T(1);
     const int nrows = nz * TE;
-    // load, scale and normalise (rows of the tile: r = z * TE + el)
-    for (int r = tid; r < nrows; r += kPcrThreads) {
+    for (int r = threadIdx.x; r < nrows; r += kPcrThreads) {
         const int z = r / TE, el = r - z * TE, e = e0 + el;
         cplx<T> x = mk<T>(T(0), T(0));
         cplx<T> bm = mk<T>(T(1), T(1));
@@ -185,6 +181,44 @@ __global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S,
         ac[2] = cx;
         ac[3] = cy;
     }
+}
+
+// Store the solved lines; the mean of the zero-mode line for the zero-mean gauge.
+template <typename Tio, int TE>
+__device__ void tri_store(cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int e0,
+                          const cplx<double>* X, double* red) {
+    const int nz = a.nz, ny = a.ny;
+    const bool sing = a.singular && m == 0;
+    double csum = 0.0;
+    for (int r = threadIdx.x; r < nz * TE; r += kPcrThreads) {
+        const int z = r / TE, el = r - z * TE, e = e0 + el;
+        if (e >= ny) continue;
+        const cplx<double> u = X[r];
+        S[base + (size_t)z * a.zstride + e] = mk<Tio>((Tio)u.x, (Tio)u.y);
+        if (sing && e == 0) csum += u.x;
+    }
+    if (m == 0 && blockIdx.x == 0) {
+        const double tot = block_sum<kPcrThreads>(csum, red);
+        if (threadIdx.x == 0) a.cmean[b] = (sing && a.demean) ? tot / (double)nz : 0.0;
+    }
+}
+
+template <typename Tio>
+__global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a) {
+    using T = double;
+    constexpr int TE = pcr_te<Tio>();
+    constexpr int ITEMS = 512 * TE / kPcrThreads;   // (entry, z) rows per thread at nz = 512
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nz = a.nz;
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int e0 = blockIdx.x * TE;
+    const int tid = threadIdx.x;
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(smem);            // [z][TE]
+    T* AC = reinterpret_cast<T*>(X + (size_t)nz * TE);         // [z][TE][4]: a.x, a.y, c.x, c.y
+    double* red = reinterpret_cast<double*>(AC + (size_t)nz * TE * 4);
+    const size_t base = (size_t)b * a.slots * nz * a.ny + (size_t)m * a.sstride;
+    const int nrows = nz * TE;
+    tri_load<Tio, TE>(S, a, base, m, b, e0, X, AC);
     __syncthreads();
     for (int s = 1; s < nz; s <<= 1) {
         cplx<T> nx_[ITEMS];
@@ -237,23 +271,92 @@ __global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S,
         }
         __syncthreads();
     }
-    // store; the mean of the zero-mode line for the zero-mean gauge
-    double csum = 0.0;
-    for (int r = tid; r < nrows; r += kPcrThreads) {
-        const int z = r / TE, el = r - z * TE, e = e0 + el;
-        if (e >= ny) continue;
-        const cplx<T> u = X[r];
-        S[base + (size_t)z * a.zstride + e] = mk<Tio>((Tio)u.x, (Tio)u.y);
-        if (sing && e == 0) csum += (double)u.x;
-    }
-    if (m == 0 && blockIdx.x == 0) {
-        const double tot = block_sum<kPcrThreads>(csum, red);
-        if (tid == 0) a.cmean[b] = (sing && a.demean) ? tot / (double)nz : 0.0;
-    }
+    tri_store<Tio, TE>(S, a, base, m, b, e0, X, red);
 }
 
+// Cyclic reduction with a parallel backward phase (section "Cyclic Reduction
+// Technique", CR-P).  Forward: at stride s = 1, 2, 4, ... (while 2s <= nz) the
+// rows z = 2s-1, 4s-1, ... are combined with rows z -+ s as in PCR,
+//     r = 1 / (1 - a_z c_{z-s} - c_z a_{z+s})
+//     a_z <- -r a_z a_{z-s},  c_z <- -r c_z c_{z+s},
+//     x_z <- r (x_z - a_z x_{z-s} - c_z x_{z+s}),
+// which leaves them coupled to rows z -+ 2s only; the rows a level reads are
+// not the rows it writes, so a level needs one barrier.  The last stride s
+// leaves the single row s-1, already decoupled (x = u).  Backward: for
+// t = s/2, ..., 1 the rows z = t-1, 3t-1, ... take u_z = x_z - a_z u_{z-t} -
+// c_z u_{z+t}, their neighbours being solved at the coarser levels.  Rows
+// outside [0, nz) count as zero.
+template <typename Tio>
+__global__ __launch_bounds__(kPcrThreads) void k_zcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a) {
+    using T = double;
+    constexpr int TE = pcr_te<Tio>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nz = a.nz;
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int e0 = blockIdx.x * TE;
+    const int tid = threadIdx.x;
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(smem);            // [z][TE]
+    T* AC = reinterpret_cast<T*>(X + (size_t)nz * TE);         // [z][TE][4]: a.x, a.y, c.x, c.y
+    double* red = reinterpret_cast<double*>(AC + (size_t)nz * TE * 4);
+    const size_t base = (size_t)b * a.slots * nz * a.ny + (size_t)m * a.sstride;
+    tri_load<Tio, TE>(S, a, base, m, b, e0, X, AC);
+    __syncthreads();
+    int s = 1;
+    for (; 2 * s <= nz; s <<= 1) {
+        const int cnt = (nz - (2 * s - 1) + 2 * s - 1) / (2 * s);   // rows 2s-1 + 2s q < nz
+        for (int w = tid; w < cnt * TE; w += kPcrThreads) {
+            const int q = w / TE, el = w - q * TE;
+            const int z = 2 * s - 1 + 2 * s * q;
+            const int r = z * TE + el;
+            T* ac = AC + (size_t)r * 4;
+            const T* am = AC + (size_t)(r - s * TE) * 4;          // z - s >= s - 1 >= 0
+            const cplx<T> xm = X[r - s * TE];
+            T ap[4] = {T(0), T(0), T(0), T(0)};
+            cplx<T> xp = mk<T>(T(0), T(0));
+            if (z + s < nz) {
+                const T* qq = AC + (size_t)(r + s * TE) * 4;
+                ap[0] = qq[0];
+                ap[1] = qq[1];
+                ap[2] = qq[2];
+                ap[3] = qq[3];
+                xp = X[r + s * TE];
+            }
+            const cplx<T> x = X[r];
+            const T rx = T(1) / (T(1) - ac[0] * am[2] - ac[2] * ap[0]);
+            const T ry = T(1) / (T(1) - ac[1] * am[3] - ac[3] * ap[1]);
+            const T a0 = -rx * ac[0] * am[0], a1 = -ry * ac[1] * am[1];
+            const T c0 = -rx * ac[2] * ap[2], c1 = -ry * ac[3] * ap[3];
+            X[r] = mk<T>(rx * (x.x - ac[0] * xm.x - ac[2] * xp.x), ry * (x.y - ac[1] * xm.y - ac[3] * xp.y));
+            ac[0] = a0;
+            ac[1] = a1;
+            ac[2] = c0;
+            ac[3] = c1;
+        }
+        __syncthreads();
+    }
+    // row s - 1 is decoupled: X already holds its solution
+    for (int t = s >> 1; t >= 1; t >>= 1) {
+        const int cnt = (nz - (t - 1) + 2 * t - 1) / (2 * t);         // rows t-1 + 2t q < nz
+        for (int w = tid; w < cnt * TE; w += kPcrThreads) {
+            const int q = w / TE, el = w - q * TE;
+            const int z = t - 1 + 2 * t * q;
+            const int r = z * TE + el;
+            const T* ac = AC + (size_t)r * 4;
+            cplx<T> um = mk<T>(T(0), T(0)), up = um;
+            if (z - t >= 0) um = X[r - t * TE];
+            if (z + t < nz) up = X[r + t * TE];
+            const cplx<T> x = X[r];
+            X[r] = mk<T>(x.x - ac[0] * um.x - ac[2] * up.x, x.y - ac[1] * um.y - ac[3] * up.y);
+        }
+        __syncthreads();
+    }
+    tri_store<Tio, TE>(S, a, base, m, b, e0, X, red);
+}
+
+// y passes around a reduction kernel on whole z lines: cr = false for PCR,
+// true for CR-P
 template <typename T>
-hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s, bool cr) {
     const dim3 gy(a.slots, (a.nz + 7) / 8, batch);
     hipLaunchKernelGGL((k_ypass<T, false>), gy, dim3(512), 0, s, S, a);
     const size_t lds = pcr_lds_bytes<T>(a.nz);
@@ -261,15 +364,18 @@ hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_
     if (!attr) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zpcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)pcr_lds_bytes<T>(512));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)pcr_lds_bytes<T>(512));
         attr = true;
     }
     const dim3 gz((a.ny + pcr_te<T>() - 1) / pcr_te<T>(), a.slots, batch);
-    hipLaunchKernelGGL((k_zpcr<T>), gz, dim3(kPcrThreads), lds, s, S, a);
+    if (cr) hipLaunchKernelGGL((k_zcr<T>), gz, dim3(kPcrThreads), lds, s, S, a);
+    else hipLaunchKernelGGL((k_zpcr<T>), gz, dim3(kPcrThreads), lds, s, S, a);
     hipLaunchKernelGGL((k_ypass<T, true>), gy, dim3(512), 0, s, S, a);
     return hipGetLastError();
 }
 
-template hipError_t launch_mid_pcr<double>(cplx<double>*, const MidArgs<double>&, int, hipStream_t);
-template hipError_t launch_mid_pcr<float>(cplx<float>*, const MidArgs<float>&, int, hipStream_t);
+template hipError_t launch_mid_pcr<double>(cplx<double>*, const MidArgs<double>&, int, hipStream_t, bool);
+template hipError_t launch_mid_pcr<float>(cplx<float>*, const MidArgs<float>&, int, hipStream_t, bool);
 
 }  // namespace pp

@@ -1,7 +1,8 @@
-"""GPU parity of the alternative z solver (parallel cyclic reduction, y
-transforms as separate passes) against the oracle, whose z solve is the
-general Thomas algorithm pinned to dense LU; and at full size against the
-backward-error bar.  Tolerances as for the default solver.
+"""GPU parity of the alternative z solvers (parallel cyclic reduction, and
+cyclic reduction with a parallel backward phase; y transforms as separate
+passes) against the oracle, whose z solve is the general Thomas algorithm
+pinned to dense LU; and at full size against the backward-error bar.
+Tolerances as for the default solver.
 """
 
 import numpy as np
@@ -12,15 +13,17 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 BCS = [x * 2 + y * 2 + z for x in "PND" for y in "PND" for z in ("DD", "NN", "DN", "ND")]
-SHAPES = [(7, 12, 16), (5, 9, 6), (3, 1, 4), (1, 4, 3), (2, 3, 1), (37, 36, 48), (20, 32, 27), (64, 8, 8)]
+SHAPES = [(7, 12, 16), (5, 9, 6), (3, 1, 4), (1, 4, 3), (2, 3, 1), (37, 36, 48), (20, 32, 27), (64, 8, 8),
+          (6, 8, 8), (33, 8, 8)]
+SOLVERS = ["pcr", "cr"]
 
 
-def _solve(f, bc, h, dtype="f64", gauge="mean", adjoint=False):
+def _solve(f, bc, h, dtype="f64", gauge="mean", adjoint=False, zsolver="pcr"):
     import torch
     from paper_1909_05423_amd import Plan
     from gpu_util import to_dev
     f = np.asarray(f)
-    plan = Plan(f.shape, bc, h, dtype=dtype, gauge=gauge, zsolver="pcr")
+    plan = Plan(f.shape, bc, h, dtype=dtype, gauge=gauge, zsolver=zsolver)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     fd = to_dev(f.reshape((1,) + f.shape), tdt)
     u = plan.adjoint(fd) if adjoint else plan.solve(fd)
@@ -28,52 +31,55 @@ def _solve(f, bc, h, dtype="f64", gauge="mean", adjoint=False):
     return u.double().cpu().numpy().reshape(f.shape), plan
 
 
+@pytest.mark.parametrize("zsolver", SOLVERS)
 @pytest.mark.parametrize("bc", BCS)
-def test_pcr_f64_all_bcs(bc):
+def test_pcr_f64_all_bcs(bc, zsolver):
     from gpu_util import banner, rel_max
     rng = np.random.default_rng(97 + sum(map(ord, bc)))
     for shape in SHAPES:
-        banner(f"pcr f64 {bc} {shape}")
+        banner(f"{zsolver} f64 {bc} {shape}")
         h = tuple(rng.uniform(0.5, 2.0, 3))
         f = rng.standard_normal(shape)
-        u, _ = _solve(f, bc, h)
+        u, _ = _solve(f, bc, h, zsolver=zsolver)
         assert rel_max(u, oracle.solve(f, bc, h, "mean")) < 1e-12, (bc, shape)
 
 
+@pytest.mark.parametrize("zsolver", SOLVERS)
 @pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDN", "NNDDND", "PPPPDD"])
-def test_pcr_f32_refined_gauges_adjoint(bc):
+def test_pcr_f32_refined_gauges_adjoint(bc, zsolver):
     from gpu_util import banner, rel_max
     rng = np.random.default_rng(101 + sum(map(ord, bc)))
     for shape in [(8, 12, 16), (37, 36, 48)]:
         h = tuple(rng.uniform(0.5, 2.0, 3))
         f = rng.standard_normal(shape) + 0.2
-        banner(f"pcr refined {bc} {shape}")
-        u, _ = _solve(f, bc, h, dtype="f32_refined")
+        banner(f"{zsolver} refined {bc} {shape}")
+        u, _ = _solve(f, bc, h, dtype="f32_refined", zsolver=zsolver)
         assert rel_max(u, oracle.solve(f, bc, h, "mean")) < 1e-12
         f32 = f.astype(np.float32).astype(np.float64)
-        banner(f"pcr f32 {bc} {shape}")
-        u, _ = _solve(f32, bc, h, dtype="f32")
+        banner(f"{zsolver} f32 {bc} {shape}")
+        u, _ = _solve(f32, bc, h, dtype="f32", zsolver=zsolver)
         assert rel_max(u, oracle.solve(f32, bc, h, "mean")) < 1e-5
         for gauge in ["pin", "pin_raw"]:
-            banner(f"pcr {gauge} {bc} {shape}")
-            u, _ = _solve(f, bc, h, gauge=gauge)
+            banner(f"{zsolver} {gauge} {bc} {shape}")
+            u, _ = _solve(f, bc, h, gauge=gauge, zsolver=zsolver)
             assert rel_max(u, oracle.solve(f, bc, h, gauge)) < 1e-12
-        banner(f"pcr adjoint {bc} {shape}")
-        v, _ = _solve(f, bc, h, adjoint=True)
+        banner(f"{zsolver} adjoint {bc} {shape}")
+        v, _ = _solve(f, bc, h, adjoint=True, zsolver=zsolver)
         assert rel_max(v, oracle.solve_adjoint(f, bc, h, "mean")) < 1e-12
 
 
-def test_pcr_full_size_backward_error_and_agreement():
-    """512^3 divergence workload: the PCR solve meets the backward-error bar and
-    agrees with the default (Thomas) solve."""
+@pytest.mark.parametrize("zsolver", SOLVERS)
+def test_pcr_full_size_backward_error_and_agreement(zsolver):
+    """512^3 divergence workload: the PCR / CR-P solve meets the backward-error
+    bar and agrees with the default (Thomas) solve."""
     import torch
     import workloads
     from paper_1909_05423_amd import Plan
     from gpu_util import banner
     wl = workloads.make("div_ppn")
     f = torch.from_numpy(wl["f"]).cuda()
-    banner("pcr 512^3 div_ppn")
-    up = Plan(wl["shape"], wl["bc"], wl["h"], zsolver="pcr").solve(f)
+    banner(f"{zsolver} 512^3 div_ppn")
+    up = Plan(wl["shape"], wl["bc"], wl["h"], zsolver=zsolver).solve(f)
     ut = Plan(wl["shape"], wl["bc"], wl["h"]).solve(f)
     torch.cuda.synchronize()
     diff = float((up - ut).abs().max() / ut.abs().max())

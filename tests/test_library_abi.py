@@ -136,16 +136,19 @@ def test_zsolver_option(lib):
     st, p = _create(lib, 8, 8, 8, "PPPPDD")
     assert st == 0
     assert lib.pp_plan_set_zsolver(p, 1) == 0
+    assert lib.pp_plan_set_zsolver(p, 2) == 0
     assert lib.pp_plan_set_zsolver(p, 0) == 0
-    assert lib.pp_plan_set_zsolver(p, 2) == -1
+    assert lib.pp_plan_set_zsolver(p, 3) == -1
+    assert lib.pp_plan_set_zsolver(p, -1) == -1
     lib.pp_plan_destroy(p)
-    st, p = _create(lib, 8, 8, 8, "PPPPPP")
-    assert st == 0 and lib.pp_plan_set_zsolver(p, 1) == -2     # periodic z: Thomas only
-    lib.pp_plan_destroy(p)
-    st, p = _create(lib, 8, 8, 1024, "PPPPDD")
-    assert st == 0 and lib.pp_plan_set_zsolver(p, 1) == -3     # z lines longer than 512
-    lib.pp_plan_destroy(p)
-    st, p = _create(lib, 8, 1024, 8, "PPPPDD")
-    assert st == 0 and lib.pp_plan_set_zsolver(p, 1) == -3     # y lines longer than 512
-    lib.pp_plan_destroy(p)
+    for solver in (1, 2):                                       # PCR, CR-P
+        st, p = _create(lib, 8, 8, 8, "PPPPPP")
+        assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -2     # periodic z: Thomas only
+        lib.pp_plan_destroy(p)
+        st, p = _create(lib, 8, 8, 1024, "PPPPDD")
+        assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -3     # z lines longer than 512
+        lib.pp_plan_destroy(p)
+        st, p = _create(lib, 8, 1024, 8, "PPPPDD")
+        assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -3     # y lines longer than 512
+        lib.pp_plan_destroy(p)
 
