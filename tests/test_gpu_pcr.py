@@ -88,3 +88,28 @@ def test_pcr_full_size_backward_error_and_agreement(zsolver):
     fh = wl["f"][0] - wl["f"][0].mean()
     eta = oracle.backward_error(fh, u, wl["bc"], wl["h"])
     assert eta < 1e-14, eta
+
+
+@pytest.mark.parametrize("zsolver", SOLVERS)
+def test_pcr_with_faces_and_batch(zsolver):
+    """Face values and a batch of two through the alternative z solvers."""
+    import torch
+    from paper_1909_05423_amd import Plan
+    from gpu_util import banner, rel_max, to_dev
+    rng = np.random.default_rng(103)
+    for bc in ["DDNNDN", "PPPPNN"]:
+        shape = (20, 32, 27)
+        nz, ny, nx = shape
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal((2,) + shape)
+        dims = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+        faces = [None if bc[i] == "P" else rng.standard_normal((2,) + dims[i]) for i in range(6)]
+        banner(f"{zsolver} faces batch 2 {bc} {shape}")
+        plan = Plan(shape, bc, h, batch=2, zsolver=zsolver)
+        u = plan.solve(to_dev(f, torch.float64),
+                       faces=[None if g is None else to_dev(g, torch.float64) for g in faces])
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()
+        for b in range(2):
+            fb = [None if g is None else g[b] for g in faces]
+            assert rel_max(u[b], oracle.solve(f[b], bc, h, "mean", faces=fb)) < 1e-12, (bc, b)
