@@ -72,6 +72,17 @@ typedef enum {
                                   library reads scalars back: refinement, last_info) */
 } pp_status;
 
+/* Limits (the plan call returns PP_ERR_SIZE beyond them):
+ *   nx, ny      factor as 2^a 3^b and are at most 2048 (whole lines are held on
+ *               chip; y lines up to 1024 take the pipelined z march, longer ones
+ *               a slower general march);
+ *   nz * batch  at most 65535 (launch grid of the refinement residual);
+ *   periodic z  nz >= 3;
+ *   PCR / CR-P  z not periodic (PP_ERR_BC), nz and ny at most 512 (set_zsolver).
+ * Device workspace: pp_plan_workspace_bytes(p); about 8 B (PP_F64, and
+ * PP_F32_REFINED) or 4 B (PP_F32) per grid point and batch entry, plus the
+ * plan tables. */
+
 /* Create a plan (host only; no GPU call).
  *   nx, ny, nz  cells per direction, >= 1.  nx and ny must factor as 2^a 3^b.
  *   bc          6 chars for the faces (x-, x+, y-, y+, z-, z+) from
@@ -119,10 +130,18 @@ size_t pp_plan_workspace_bytes(pp_plan p);
 
 /* Solve L_h u = f for every batch entry.  f and u: device arrays of
  * batch*nz*ny*nx doubles (PP_F64, PP_F32_REFINED) or floats (PP_F32); they
- * must not overlap each other or the workspace.  The first call with a given
- * workspace pointer uploads the plan's tables into it (an asynchronous copy on
- * `stream`); later calls with the same pointer reuse them, so the workspace
- * must not be modified between solves.  f is read only. */
+ * must not overlap each other or the workspace.  f is read only.
+ * Workspace ownership: the library records, per workspace base pointer, which
+ * plan last uploaded its tables there.  A call with a workspace that this plan
+ * did not fill last uploads the plan's tables into it (an asynchronous copy on
+ * `stream`); later calls reuse them.  So several plans may share one workspace
+ * (each call then re-uploads when the previous one was another plan's), but
+ * the caller must not write into a workspace between solves, must not pass
+ * workspaces of different plans that overlap without starting at the same
+ * address, and must not free a workspace and hand a new allocation at the same
+ * address to the plan that used the old one (its tables would be taken as
+ * present).  The Python binding allocates one workspace per plan and holds it
+ * for the plan's lifetime. */
 pp_status pp_solve(pp_plan p, const void* f, void* u, void* workspace, void* stream);
 
 /* Solve with non-homogeneous face values (section "Boundary Conditions":

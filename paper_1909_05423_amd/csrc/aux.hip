@@ -21,13 +21,13 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize_xfwd(const double* __r
         double s = 0.0, mx = 0.0;
         for (int i = threadIdx.x; i < nper; i += kRedThreads) {
             s += partial[2 * ((size_t)b * nper + i)];
-            mx = fmax(mx, partial[2 * ((size_t)b * nper + i) + 1]);
+            mx = nmax(mx, partial[2 * ((size_t)b * nper + i) + 1]);
         }
         const double bs = block_sum<kRedThreads>(s, red);
         const double bm = block_max<kRedThreads>(mx, red);
         if (threadIdx.x == 0) {
             mu[b] = bs / npts;
-            gmax = fmax(gmax, bm);
+            gmax = nmax(gmax, bm);
         }
     }
     if (threadIdx.x == 0 && maxf) *maxf = gmax;
@@ -53,20 +53,20 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize_update(const double* _
         for (int i = threadIdx.x; i < nper; i += kRedThreads) {
             const size_t k = 3 * ((size_t)b * nper + i);
             s += partial[k];
-            md = fmax(md, partial[k + 1]);
-            mu = fmax(mu, partial[k + 2]);
+            md = nmax(md, partial[k + 1]);
+            mu = nmax(mu, partial[k + 2]);
         }
         const double bs = block_sum<kRedThreads>(s, red);
         const double bd = block_max<kRedThreads>(md, red);
         const double bu = block_max<kRedThreads>(mu, red);
         if (threadIdx.x == 0) {
             sc[SC_COUNT + 2 * batch + b] = nregion > 0.0 ? bs / nregion : 0.0;
-            gd = fmax(gd, bd);
-            gu = fmax(gu, bu);
+            gd = nmax(gd, bd);
+            gu = nmax(gu, bu);
         }
     }
     if (threadIdx.x == 0) {
-        const double rel = gu > 0.0 ? gd / gu : 0.0;
+        const double rel = (gu == 0.0) ? 0.0 : gd / gu;   // NaN stays NaN
         sc[SC_RELPREV] = first ? 1.0 : sc[SC_REL];
         sc[SC_MAXD] = gd;
         sc[SC_MAXU] = gu;

@@ -16,6 +16,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -54,7 +56,7 @@ struct pp_plan_s {
     size_t table_rows = 0;
     // workspace layout (byte offsets)
     size_t o_scalars = 0, o_partial = 0, o_tables = 0, o_S = 0, o_r = 0, ws_bytes = 0;
-    const void* bound_ws = nullptr;
+    unsigned long long serial = 0;   // identifies the plan in the workspace registry
     // last call
     void* last_ws = nullptr;
     hipStream_t last_stream = nullptr;
@@ -75,6 +77,31 @@ struct pp_plan_s {
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Which plan's tables each workspace holds: workspace base pointer -> serial
+// number of the plan that last uploaded its tables there.  A solve re-uploads
+// the tables when the workspace it is given was last used by another plan
+// (two plans sharing one workspace, the fixed buffer of pp_solve_noalloc).
+std::mutex g_ws_mu;
+std::map<const void*, unsigned long long> g_ws_owner;
+unsigned long long g_next_serial = 1;
+
+bool tables_present(const pp_plan p, const void* ws) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    const auto it = g_ws_owner.find(ws);
+    return it != g_ws_owner.end() && it->second == p->serial;
+}
+void tables_uploaded(const pp_plan p, const void* ws) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    g_ws_owner[ws] = p->serial;
+}
+void forget_plan(const pp_plan p) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    for (auto it = g_ws_owner.begin(); it != g_ws_owner.end();) {
+        if (it->second == p->serial) it = g_ws_owner.erase(it);
+        else ++it;
+    }
+}
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int bc_code(char c) {
@@ -740,9 +767,9 @@ pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* str
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
-    if (p->bound_ws != workspace) {
+    if (!tables_present(p, workspace)) {
         PP_HIP(hipMemcpyAsync(ws + p->o_tables, p->blob.data(), p->blob.size(), hipMemcpyHostToDevice, s));
-        p->bound_ws = workspace;
+        tables_uploaded(p, workspace);
     }
     // zero-mode treatment; the adjoint trades projection and mean shift
     bool project, demean;
@@ -808,6 +835,10 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
 
     pp_plan p = new (std::nothrow) pp_plan_s;
     if (!p) return PP_ERR_ARG;
+    {
+        std::lock_guard<std::mutex> lock(g_ws_mu);
+        p->serial = g_next_serial++;
+    }
     p->nx = nx;
     p->ny = ny;
     p->nz = nz;
@@ -971,7 +1002,9 @@ pp_status pp_plan_kernel_times(pp_plan p, double* ms, int* launches, int reset) 
 }
 
 void pp_plan_destroy(pp_plan p) {
-    if (p) (void)collect(p);
+    if (!p) return;
+    (void)collect(p);
+    forget_plan(p);
     delete p;
 }
 

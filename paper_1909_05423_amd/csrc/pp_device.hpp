@@ -337,6 +337,10 @@ __device__ __forceinline__ void w512_last(const cplx<T>* line, const TW& w, int 
     bfly8<INV, T>(v);
 }
 
+// Maximum that keeps a NaN from either argument (fmax drops it), so that a
+// non-finite source or solution reaches the scalars the host checks.
+__device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
 // Sum of a double over the block (wave64 shuffles, then LDS across waves).
 // Result valid in thread 0.
 template <int NTH> __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -355,13 +359,13 @@ template <int NTH> __device__ __forceinline__ double block_sum(double v, double*
 
 template <int NTH> __device__ __forceinline__ double block_max(double v, double* red) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    for (int off = 32; off > 0; off >>= 1) v = nmax(v, __shfl_down(v, off, 64));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0) {
-        for (int w = 0; w < NTH / 64; ++w) s = fmax(s, red[w]);
+        for (int w = 0; w < NTH / 64; ++w) s = nmax(s, red[w]);
     }
     __syncthreads();
     return s;

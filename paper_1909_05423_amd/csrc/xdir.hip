@@ -76,7 +76,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    for (int off = 32; off > 0; off >>= 1) v = nmax(v, __shfl_down(v, off, 64));
     return v;
 }
 
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                 }
                 const double fa_ = (double)ra[r] - la, fb_ = (double)rb[r] - lb;
                 acc += fa_ + fb_;
-                amax = fmax(amax, fmax(fabs(fa_), fabs(fb_)));
+                amax = nmax(amax, nmax(fabs(fa_), fabs(fb_)));
                 T va = (T)fa_, vb = (T)fb_;
                 int pos = n;
                 if (a.bx != BC_P) {
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                         const double lb = face_lift_yz(fa, xb.b, n, ya + 1, xb.z, nx, ny, nz);
                         const double fa_ = (double)vf[r].x - la, fb_ = (double)vf[r].y - lb;
                         acc -= la + lb;
-                        amax = fmax(amax, fmax(fabs(fa_), fabs(fb_)));
+                        amax = nmax(amax, nmax(fabs(fa_), fabs(fb_)));
                         vf[r] = mk<T>((T)fa_, (T)fb_);
                     }
                 }
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                     cplx<T>& v = lds[j * ldl + pad(pos)];
                     const double fa_ = sg * (double)v.x - la, fb_ = sg * (double)v.y - lb;
                     acc -= la + lb;
-                    amax = fmax(amax, fmax(fabs(fa_), fabs(fb_)));
+                    amax = nmax(amax, nmax(fabs(fa_), fabs(fb_)));
                     v = mk<T>((T)(sg * fa_), (T)(sg * fb_));
                 }
             }
@@ -581,8 +581,8 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                             const double un = uo[UR > 1 ? 2 * k + part : 0] + d - gshift;   // uo = 0 for XINV_FIRST
                             st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
-                            dmax = fmax(dmax, fabs(d));
-                            umax = fmax(umax, fabs(un));
+                            dmax = nmax(dmax, fabs(d));
+                            umax = nmax(umax, fabs(un));
                         }
                     }
                 }
@@ -605,8 +605,8 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                             const double un = (MODE == XINV_UPDATE ? (double)dst[idx] : 0.0) + d - gshift;
                             st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
-                            dmax = fmax(dmax, fabs(d));
-                            umax = fmax(umax, fabs(un));
+                            dmax = nmax(dmax, fabs(d));
+                            umax = nmax(umax, fabs(un));
                         }
                     }
                 }
