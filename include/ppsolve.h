@@ -68,8 +68,10 @@ typedef enum {
     PP_ERR_WORKSPACE = -5,     /* workspace pointer null or misaligned (256 B) */
     PP_ERR_HIP = -6,           /* a HIP call failed (launch, copy, synchronisation) */
     PP_ERR_NOT_CONVERGED = -7, /* refinement did not reach its tolerance in max_iter steps */
-    PP_ERR_NONFINITE = -8      /* the source held an Inf or NaN (reported where the
+    PP_ERR_NONFINITE = -8,     /* the source held an Inf or NaN (reported where the
                                   library reads scalars back: refinement, last_info) */
+    PP_ERR_SCRATCH = -9        /* pp_solve_noalloc: the plan needs more workspace than
+                                  PP_NOALLOC_SCRATCH_BYTES */
 } pp_status;
 
 /* Limits (the plan call returns PP_ERR_SIZE beyond them):
@@ -189,6 +191,21 @@ pp_status pp_plan_last_info(pp_plan p, int* ir_iters, double* removed_mean, doub
  * (arrays of 4; either may be NULL); reset != 0 clears the accumulators. */
 pp_status pp_plan_set_timing(pp_plan p, int on);
 pp_status pp_plan_kernel_times(pp_plan p, double* ms, int* launches, int reset);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * pp_solve with the workspace replaced by a fixed buffer of
+ * PP_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * (from the first use until the process ends).  Calls no allocator.  Same f, u,
+ * stream and error rules as pp_solve (face values and the adjoint are not
+ * offered here), plus PP_ERR_SCRATCH when pp_plan_workspace_bytes(p) exceeds
+ * the buffer.  Every call on one device shares that device's buffer: calls
+ * that overlap in time on one device (other streams, other threads) race and
+ * must be ordered by the caller.  The first call of a plan after another plan
+ * used the buffer copies the plan's tables into it from host memory (so a
+ * caller capturing a graph makes one call before the capture). */
+#define PP_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+pp_status pp_solve_noalloc(pp_plan p, const void* f, void* u, void* stream);
 
 void pp_plan_destroy(pp_plan p);
 

@@ -17,13 +17,17 @@ PP_GAUGE_MEAN, PP_GAUGE_PIN, PP_GAUGE_PIN_RAW = 0, 1, 2
 STATUS = {
     0: "PP_OK", -1: "PP_ERR_ARG", -2: "PP_ERR_BC", -3: "PP_ERR_SIZE", -4: "PP_ERR_ALIAS",
     -5: "PP_ERR_WORKSPACE", -6: "PP_ERR_HIP", -7: "PP_ERR_NOT_CONVERGED", -8: "PP_ERR_NONFINITE",
+    -9: "PP_ERR_SCRATCH",
 }
+
+# size of the fixed workspace behind pp_solve_noalloc (PP_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 EXPORTED = [
     "pp_plan_create", "pp_plan_set_gauge", "pp_plan_set_zsolver", "pp_plan_set_refinement",
     "pp_plan_workspace_bytes",
     "pp_solve", "pp_solve_bc", "pp_solve_adjoint", "pp_plan_last_info", "pp_plan_set_timing", "pp_plan_kernel_times",
-    "pp_plan_destroy", "pp_status_string",
+    "pp_plan_destroy", "pp_status_string", "pp_solve_noalloc",
 ]
 
 _lib = None
@@ -60,6 +64,8 @@ def load():
     lib.pp_solve.restype = i
     lib.pp_solve_bc.argtypes = [vp, vp, ctypes.POINTER(vp), vp, vp, vp]
     lib.pp_solve_bc.restype = i
+    lib.pp_solve_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.pp_solve_noalloc.restype = i
     lib.pp_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.pp_solve_adjoint.restype = i
     lib.pp_plan_last_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(d)]

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB_NAME = "libppsolve.so"
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "xdir.hip", "zmarch.hip", "zpcr.hip", "aux.hip"]
+SOURCES = ["plan.cpp", "xdir.hip", "zmarch.hip", "zpcr.hip", "aux.hip", "scratch.hip"]
 
 
 def hipcc_path():

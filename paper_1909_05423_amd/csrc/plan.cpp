@@ -1001,6 +1001,19 @@ pp_status pp_plan_kernel_times(pp_plan p, double* ms, int* launches, int reset) 
     return PP_OK;
 }
 
+pp_status pp_solve_noalloc(pp_plan p, const void* f, void* u, void* stream) {
+    if (!p || !f || !u) return PP_ERR_ARG;
+    if (p->ws_bytes > pp::kScratchBytes) return PP_ERR_SCRATCH;
+    void* ws = nullptr;
+    if (pp::scratch_buffer(&ws) != hipSuccess) return PP_ERR_HIP;
+    // no timing events here: creating them is a runtime allocation
+    const bool timing = p->timing;
+    p->timing = false;
+    const pp_status st = dispatch(p, f, u, ws, stream, false);
+    p->timing = timing;
+    return st;
+}
+
 void pp_plan_destroy(pp_plan p) {
     if (!p) return;
     (void)collect(p);
@@ -1019,6 +1032,7 @@ const char* pp_status_string(pp_status st) {
         case PP_ERR_HIP: return "HIP runtime error";
         case PP_ERR_NOT_CONVERGED: return "refinement did not converge";
         case PP_ERR_NONFINITE: return "non-finite value in the source";
+        case PP_ERR_SCRATCH: return "problem needs more workspace than the fixed no-alloc buffer holds";
     }
     return "unknown status";
 }

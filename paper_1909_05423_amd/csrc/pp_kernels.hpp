@@ -6,6 +6,7 @@
 #include <cstddef>
 
 #include "pp_device.hpp"
+#include "../../include/ppsolve.h"
 
 namespace pp {
 
@@ -187,6 +188,11 @@ hipError_t launch_residual(const double* f, const double* u, float* r, const Res
 
 // Initial scalars of the refinement loop (unit scale, no gauge shift).
 hipError_t launch_ir_init(double* scalars, int batch, hipStream_t s);
+
+// Fixed workspace of pp_solve_noalloc (one per device, inside the library).
+constexpr size_t kScratchBytes = (size_t)PP_NOALLOC_SCRATCH_BYTES;
+// Device address of this device's fixed workspace (looked up once per device).
+hipError_t scratch_buffer(void** ptr);
 
 // Scalar block layout (doubles) used by the refinement loop.
 enum Scalar : int {

@@ -126,6 +126,17 @@ class Plan:
 
         return self._run(call, f, out, "pp_solve_bc")
 
+    def solve_noalloc(self, f, out=None):
+        """solve() through pp_solve_noalloc: the library's fixed per-device
+        workspace instead of this plan's (no device allocation in the call when
+        out is given)."""
+        lib = _lib.load()
+
+        def call(plan, src, dst, ws, stream):
+            return lib.pp_solve_noalloc(plan, src, dst, stream)
+
+        return self._run(call, f, out, "pp_solve_noalloc")
+
     def adjoint(self, g, out=None):
         """G^T g for the map G: f -> u of solve()."""
         return self._run(_lib.load().pp_solve_adjoint, g, out, "pp_solve_adjoint")

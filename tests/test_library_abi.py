@@ -152,3 +152,26 @@ def test_zsolver_option(lib):
         assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -3     # y lines longer than 512
         lib.pp_plan_destroy(p)
 
+
+
+def test_noalloc_rejects_before_touching_the_gpu(lib):
+    """pp_solve_noalloc: argument errors and the fixed-buffer limit are host checks."""
+    from paper_1909_05423_amd import _lib
+    st, p = _create(lib, 256, 256, 256, "PPPPNN", h=(1 / 256,) * 3, dtype=0)
+    assert st == 0
+    try:
+        assert lib.pp_plan_workspace_bytes(p) > _lib.NOALLOC_SCRATCH_BYTES
+        dummy = ctypes.c_void_p(256)
+        assert lib.pp_solve_noalloc(p, dummy, ctypes.c_void_p(512), None) == -9
+        assert lib.pp_solve_noalloc(p, None, dummy, None) == -1
+        assert lib.pp_solve_noalloc(None, dummy, dummy, None) == -1
+    finally:
+        lib.pp_plan_destroy(p)
+    assert b"no-alloc" in lib.pp_status_string(-9)
+
+
+def test_noalloc_limit_matches_header():
+    from paper_1909_05423_amd import _lib
+    text = open(HEADER).read()
+    m = re.search(r"#define PP_NOALLOC_SCRATCH_BYTES \((\d+)u \* 1024u \* 1024u\)", text)
+    assert m and int(m.group(1)) * 1024 * 1024 == _lib.NOALLOC_SCRATCH_BYTES
