@@ -122,8 +122,12 @@ struct ResPlane {
     double f;                // source
 };
 
-__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, const double* __restrict__ u,
-                                                  float* __restrict__ r, ResidualArgs a,
+// Tu: the solution's type (float for the first solve of the refinement, double
+// after); Tr: the residual's (double where its float rounding would limit the
+// next correction, see the plan code).
+template <typename Tu, typename Tr>
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, const Tu* __restrict__ u,
+                                                  Tr* __restrict__ r, ResidualArgs a,
                                                   const double* __restrict__ sc) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     const int j = blockIdx.y * 4 + threadIdx.y;
@@ -134,28 +138,28 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
     const int z1 = min(z0 + kResZ, a.nz);
     const long plane = (long)a.nx * a.ny;
     const size_t base = (size_t)b * a.nz * plane + (size_t)j * a.nx + i;
-    const double* ub = u + base;
+    const Tu* ub = u + base;
     const double* fb = f + base;
     const double mu = a.proj ? sc[SC_COUNT + 3 * a.batch + b] : 0.0;
     const double scale = sc[SC_SCALE];
     const Nbr xm = neighbour(i, a.nx, 1, -1, a.bc[0]), xp = neighbour(i, a.nx, 1, 1, a.bc[1]);
     const Nbr ym = neighbour(j, a.ny, a.nx, -1, a.bc[2]), yp = neighbour(j, a.ny, a.nx, 1, a.bc[3]);
     auto load = [&](int k) {
-        const double* p = ub + (long)k * plane;
+        const Tu* p = ub + (long)k * plane;
         const Nbr zp = neighbour(k, a.nz, plane, 1, a.bc[5]);
         ResPlane v;
-        v.xm = xm.sgn * p[xm.off];
-        v.xp = xp.sgn * p[xp.off];
-        v.ym = ym.sgn * p[ym.off];
-        v.yp = yp.sgn * p[yp.off];
-        v.up = zp.sgn * p[zp.off];
+        v.xm = xm.sgn * (double)p[xm.off];
+        v.xp = xp.sgn * (double)p[xp.off];
+        v.ym = ym.sgn * (double)p[ym.off];
+        v.yp = yp.sgn * (double)p[yp.off];
+        v.up = zp.sgn * (double)p[zp.off];
         v.f = ld_stream(fb + (long)k * plane);
         return v;
     };
     // window: below, centre
-    double uc = ub[(long)z0 * plane];
+    double uc = (double)ub[(long)z0 * plane];
     const Nbr zm = neighbour(z0, a.nz, plane, -1, a.bc[4]);
-    double ud = zm.sgn * ub[(long)z0 * plane + zm.off];
+    double ud = zm.sgn * (double)ub[(long)z0 * plane + zm.off];
     ResPlane cur = load(z0);
     for (int k = z0; k < z1; ++k) {
         const ResPlane nxt = load(min(k + 1, z1 - 1));   // the last pass re-reads its own plane
@@ -171,20 +175,27 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, 
         if (a.has_faces) fi -= face_lift(a.faces, b, i, j, k, a.nx, a.ny, a.nz);
         if (a.proj == 1) fi -= mu;
         else if (a.proj == 2 && k == 0) fi -= (double)a.nz * mu;
-        st_stream(r + base + (size_t)k * plane, (float)((fi - lap) * scale));
+        st_stream(r + base + (size_t)k * plane, (Tr)((fi - lap) * scale));
         ud = uc;
         uc = cur.up;
         cur = nxt;
     }
 }
 
-hipError_t launch_residual(const double* f, const double* u, float* r, const ResidualArgs& a, const double* scalars,
+template <typename Tu, typename Tr>
+hipError_t launch_residual(const double* f, const Tu* u, Tr* r, const ResidualArgs& a, const double* scalars,
                            hipStream_t s) {
     const int nzc = (a.nz + kResZ - 1) / kResZ;
     dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, nzc * a.batch);
-    hipLaunchKernelGGL(k_residual, grid, dim3(64, 4), 0, s, f, u, r, a, scalars);
+    hipLaunchKernelGGL((k_residual<Tu, Tr>), grid, dim3(64, 4), 0, s, f, u, r, a, scalars);
     return hipGetLastError();
 }
+template hipError_t launch_residual<float, double>(const double*, const float*, double*, const ResidualArgs&,
+                                                   const double*, hipStream_t);
+template hipError_t launch_residual<double, double>(const double*, const double*, double*, const ResidualArgs&,
+                                                    const double*, hipStream_t);
+template hipError_t launch_residual<double, float>(const double*, const double*, float*, const ResidualArgs&,
+                                                   const double*, hipStream_t);
 
 // Set the scalars that the first (unrefined) float solve reads in update mode.
 __global__ void k_ir_init(double* sc, int batch) {

@@ -27,6 +27,19 @@
 
 using pp::cplx;
 
+// Host tables of one precision and their byte offsets inside the blob.
+struct Tables {
+    std::vector<unsigned char> blob;
+    size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
+    size_t t_elen = 0;
+    size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
+    // periodic z (Sherman-Morrison)
+    size_t t_aelen = 0, t_qelen = 0;
+    size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
+           t_invgam = 0;
+    size_t table_rows = 0;
+};
+
 struct pp_plan_s {
     int nx = 0, ny = 0, nz = 0, batch = 0;
     char bc[6] = {0};
@@ -43,19 +56,18 @@ struct pp_plan_s {
     pp::FftDesc fx{}, fy{};
     int ty = 0, ldl = 0, ldy = 0, zb = 0;
     size_t nper = 0;  // upper bound of the x-kernel partial records per batch entry
-    // tables (uploaded into the workspace)
-    std::vector<unsigned char> blob;
-    size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
-    size_t t_elen = 0;
-    size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
+    // tables (uploaded into the workspace): tb[0] in the solve precision; for
+    // PP_F32_REFINED also tb[1] in double (the double-arithmetic x transform and
+    // the slots the mixed march runs in double)
+    Tables tb[2];
+    int ntab = 1;
     int zsolver = 0;     // 0 Thomas (fused march), 1 PCR, 2 CR-P
-    // periodic z (Sherman-Morrison)
-    size_t t_aelen = 0, t_qelen = 0;
-    size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
-           t_invgam = 0;
-    size_t table_rows = 0;
-    // workspace layout (byte offsets)
-    size_t o_scalars = 0, o_partial = 0, o_tables = 0, o_S = 0, o_r = 0, ws_bytes = 0;
+    // refined solve: slots lo0 .. lo0+nlo-1 kept in double by the x transform and the z march
+    int lo0 = 0, nlo = 0;
+    // workspace layout (byte offsets): o_tab[i] holds tb[i]; o_S the spectral
+    // array; refined: o_r the float residual, o_u0 the float first solution,
+    // o_lo the double slots
+    size_t o_scalars = 0, o_partial = 0, o_tab[2] = {0, 0}, o_S = 0, o_r = 0, o_u0 = 0, o_lo = 0, ws_bytes = 0;
     unsigned long long serial = 0;   // identifies the plan in the workspace registry
     // last call
     void* last_ws = nullptr;
@@ -290,9 +302,9 @@ void pivots(double lam, int nz, double hz, int bz0, int bz1, bool pinned, Line<T
     for (int i = 0; i < L; ++i) out->body[i] = (T)seq[i];
 }
 
-template <typename T> void build_tables(pp_plan p) {
-    p->blob.clear();
-    Emit<T> em{p->blob};
+template <typename T> void build_tables(pp_plan p, Tables& tb) {
+    tb.blob.clear();
+    Emit<T> em{tb.blob};
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     // FFT twiddles packed by stage (the layout the wavefront FFT reads): the
     // stage with sub-transform length Ls and radix R holds exp(-2 pi i t k step / n),
@@ -320,8 +332,8 @@ template <typename T> void build_tables(pp_plan p) {
             em.cp(*mkt)[k] = pp::mk<T>((T)c, (T)-s);
         }
     };
-    twiddles(p->fx, &p->t_twx, &p->t_mkx);
-    twiddles(p->fy, &p->t_twy, &p->t_mky);
+    twiddles(p->fx, &tb.t_twx, &tb.t_mkx);
+    twiddles(p->fy, &tb.t_twy, &tb.t_mky);
 
     std::vector<double> lamx(nx), lamy(ny);
     for (int k = 0; k < nx; ++k) lamx[k] = eigenvalue(p->bx, k, nx, p->h[0]);
@@ -379,22 +391,22 @@ template <typename T> void build_tables(pp_plan p) {
         lmax[m] = lm;
         rows += lm;
     }
-    p->table_rows = rows;
-    p->t_rowoff = em.put(sizeof(int) * slots);
-    std::memcpy(p->blob.data() + p->t_rowoff, rowoff.data(), sizeof(int) * slots);
-    p->t_lmax = em.put(sizeof(int) * slots);
-    std::memcpy(p->blob.data() + p->t_lmax, lmax.data(), sizeof(int) * slots);
+    tb.table_rows = rows;
+    tb.t_rowoff = em.put(sizeof(int) * slots);
+    std::memcpy(tb.blob.data() + tb.t_rowoff, rowoff.data(), sizeof(int) * slots);
+    tb.t_lmax = em.put(sizeof(int) * slots);
+    std::memcpy(tb.blob.data() + tb.t_lmax, lmax.data(), sizeof(int) * slots);
     // per-entry lengths: a lane reads its table row only while its entry's
     // pivots still change, so slots with a few slowly converging entries (the
     // smallest wavenumbers) do not read whole rows for most of z
-    p->t_elen = em.put(sizeof(int) * elen.size());
-    std::memcpy(p->blob.data() + p->t_elen, elen.data(), sizeof(int) * elen.size());
-    p->t_winf = em.put(sizeof(T) * winf.size());
-    std::memcpy(p->blob.data() + p->t_winf, winf.data(), sizeof(T) * winf.size());
-    p->t_wlast = em.put(sizeof(T) * wlast.size());
-    std::memcpy(p->blob.data() + p->t_wlast, wlast.data(), sizeof(T) * wlast.size());
-    p->t_wrows = em.put(sizeof(T) * 2 * std::max<size_t>(rows, 1) * ny);
-    T* wr = reinterpret_cast<T*>(p->blob.data() + p->t_wrows);
+    tb.t_elen = em.put(sizeof(int) * elen.size());
+    std::memcpy(tb.blob.data() + tb.t_elen, elen.data(), sizeof(int) * elen.size());
+    tb.t_winf = em.put(sizeof(T) * winf.size());
+    std::memcpy(tb.blob.data() + tb.t_winf, winf.data(), sizeof(T) * winf.size());
+    tb.t_wlast = em.put(sizeof(T) * wlast.size());
+    std::memcpy(tb.blob.data() + tb.t_wlast, wlast.data(), sizeof(T) * wlast.size());
+    tb.t_wrows = em.put(sizeof(T) * 2 * std::max<size_t>(rows, 1) * ny);
+    T* wr = reinterpret_cast<T*>(tb.blob.data() + tb.t_wrows);
     for (int m = 0; m < slots; ++m) {
         for (int z = 0; z < lmax[m]; ++z) {
             T* row = wr + (size_t)(rowoff[m] + z) * ny * 2;
@@ -409,8 +421,8 @@ template <typename T> void build_tables(pp_plan p) {
     // interior diagonal hz^2 lam - 2 of every z-system (PCR); padding parts get a
     // harmless non-singular value (their right-hand side is zero)
     {
-        p->t_bmid = em.put(sizeof(T) * 2 * (size_t)slots * ny);
-        T* bm = reinterpret_cast<T*>(p->blob.data() + p->t_bmid);
+        tb.t_bmid = em.put(sizeof(T) * 2 * (size_t)slots * ny);
+        T* bm = reinterpret_cast<T*>(tb.blob.data() + tb.t_bmid);
         const double hz2 = p->h[2] * p->h[2];
         for (int m = 0; m < slots; ++m) {
             const bool pairslot = (p->bx != pp::BC_P) || (m == 0);
@@ -438,7 +450,7 @@ template <typename T> void build_tables(pp_plan p) {
                 elen[(size_t)m * ny + e] = (int)std::max((lines[m][(size_t)e * 2].*vec).size(),
                                                          (lines[m][(size_t)e * 2 + 1].*vec).size());
         *t_elen = em.put(sizeof(int) * elen.size());
-        std::memcpy(p->blob.data() + *t_elen, elen.data(), sizeof(int) * elen.size());
+        std::memcpy(tb.blob.data() + *t_elen, elen.data(), sizeof(int) * elen.size());
         size_t nrows = 0;
         for (int m = 0; m < slots; ++m) {
             int L = 0;
@@ -448,11 +460,11 @@ template <typename T> void build_tables(pp_plan p) {
             nrows += L;
         }
         *t_off = em.put(sizeof(int) * slots);
-        std::memcpy(p->blob.data() + *t_off, off.data(), sizeof(int) * slots);
+        std::memcpy(tb.blob.data() + *t_off, off.data(), sizeof(int) * slots);
         *t_len = em.put(sizeof(int) * slots);
-        std::memcpy(p->blob.data() + *t_len, len.data(), sizeof(int) * slots);
+        std::memcpy(tb.blob.data() + *t_len, len.data(), sizeof(int) * slots);
         *t_rows = em.put(sizeof(T) * 2 * std::max<size_t>(nrows, 1) * ny);
-        T* rr = reinterpret_cast<T*>(p->blob.data() + *t_rows);
+        T* rr = reinterpret_cast<T*>(tb.blob.data() + *t_rows);
         for (int m = 0; m < slots; ++m)
             for (int z = 0; z < len[m]; ++z)
                 for (int e = 0; e < ny; ++e)
@@ -461,19 +473,19 @@ template <typename T> void build_tables(pp_plan p) {
                         rr[((size_t)(off[m] + z) * ny + e) * 2 + part] = (z < (int)v.size()) ? v[z] : T(0);
                     }
     };
-    emit_rows(&Line<T>::alpha, &p->t_aoff, &p->t_alen, &p->t_arows, &p->t_aelen);
-    emit_rows(&Line<T>::qp, &p->t_qoff, &p->t_qlen, &p->t_qrows, &p->t_qelen);
+    emit_rows(&Line<T>::alpha, &tb.t_aoff, &tb.t_alen, &tb.t_arows, &tb.t_aelen);
+    emit_rows(&Line<T>::qp, &tb.t_qoff, &tb.t_qlen, &tb.t_qrows, &tb.t_qelen);
     auto emit_scalar = [&](T Line<T>::*field, size_t* t) {
         *t = em.put(sizeof(T) * 2 * (size_t)slots * ny);
-        T* v = reinterpret_cast<T*>(p->blob.data() + *t);
+        T* v = reinterpret_cast<T*>(tb.blob.data() + *t);
         for (int m = 0; m < slots; ++m)
             for (int e = 0; e < ny; ++e)
                 for (int part = 0; part < 2; ++part)
                     v[((size_t)m * ny + e) * 2 + part] = lines[m][(size_t)e * 2 + part].*field;
     };
-    emit_scalar(&Line<T>::qlast, &p->t_qlast);
-    emit_scalar(&Line<T>::inv_den, &p->t_invden);
-    emit_scalar(&Line<T>::inv_gamma, &p->t_invgam);
+    emit_scalar(&Line<T>::qlast, &tb.t_qlast);
+    emit_scalar(&Line<T>::inv_den, &tb.t_invden);
+    emit_scalar(&Line<T>::inv_gamma, &tb.t_invgam);
 }
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -499,7 +511,26 @@ void spectral_strides(pp_plan p, long* sstride, long* zstride) {
     }
 }
 
-template <typename T> pp::XArgs<T> make_xargs(pp_plan p, unsigned char* ws) {
+// Refined solve: the spectral slots of the smallest x wavenumbers, whose z
+// systems are the least well conditioned, are kept in double by the forward x
+// transform and solved in double by the mixed z march.  Float rounding of
+// their spectra (which mix every y wavenumber) and of their y transforms and
+// recurrences is amplified by up to |lam_max / lam| in the solution; in the
+// other slots |lam_x| alone bounds that factor.  Periodic and cosine x hold
+// those wavenumbers in the first slots, sine x (columns stored reversed) in
+// the last.  Only where the mixed march exists (otherwise the refinement
+// simply takes more corrections).
+constexpr int kMixedSlots = 16;
+void set_mixed_slots(pp_plan p) {
+    p->nlo = 0;
+    p->lo0 = 0;
+    if (!pp::mixed_march_supported(p->ny, p->zsolver)) return;
+    p->nlo = std::min(p->slots, kMixedSlots);
+    p->lo0 = (p->bx == pp::BC_D) ? p->slots - p->nlo : 0;
+}
+
+template <typename T> pp::XArgs<T> make_xargs(pp_plan p, unsigned char* ws, int set = 0) {
+    const Tables& tb = p->tb[set];
     pp::XArgs<T> a{};
     a.nx = p->nx;
     a.ny = p->ny;
@@ -510,16 +541,21 @@ template <typename T> pp::XArgs<T> make_xargs(pp_plan p, unsigned char* ws) {
     a.ldl = p->ldl;
     spectral_strides(p, &a.sstride, &a.zstride);
     a.fx = p->fx;
-    unsigned char* t = ws + p->o_tables;
-    a.twx = reinterpret_cast<const cplx<T>*>(t + p->t_twx);
-    a.mkx = reinterpret_cast<const cplx<T>*>(t + p->t_mkx);
+    unsigned char* t = ws + p->o_tab[set];
+    a.twx = reinterpret_cast<const cplx<T>*>(t + tb.t_twx);
+    a.mkx = reinterpret_cast<const cplx<T>*>(t + tb.t_mkx);
+    a.lo0 = 0;
+    a.nlo = 0;
+    a.slo = nullptr;
     return a;
 }
 
 // Per-batch arrays after the fixed scalars: [0, B) mean of the right-hand side
 // of the current solve, [B, 2B) mean of the zero-mode solution line, [2B, 3B)
 // gauge shift of the refinement loop, [3B, 4B) mean of the source f.
-template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool demean) {
+template <typename T>
+pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool demean, int set = 0) {
+    const Tables& tb = p->tb[set];
     pp::MidArgs<T> a{};
     a.ny = p->ny;
     a.nz = p->nz;
@@ -535,32 +571,32 @@ template <typename T> pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, 
     a.scale = (T)(p->h[2] * p->h[2] / ((double)p->nx * (double)p->ny));
     a.hz2 = p->h[2] * p->h[2];
     a.fy = p->fy;
-    unsigned char* t = ws + p->o_tables;
-    a.twy = reinterpret_cast<const cplx<T>*>(t + p->t_twy);
-    a.mky = reinterpret_cast<const cplx<T>*>(t + p->t_mky);
-    a.rowoff = reinterpret_cast<const int*>(t + p->t_rowoff);
-    a.lmax = reinterpret_cast<const int*>(t + p->t_lmax);
-    a.elen = reinterpret_cast<const int*>(t + p->t_elen);
-    a.wrows = reinterpret_cast<const cplx<T>*>(t + p->t_wrows);
-    a.winf = reinterpret_cast<const cplx<T>*>(t + p->t_winf);
-    a.wlast = reinterpret_cast<const cplx<T>*>(t + p->t_wlast);
+    unsigned char* t = ws + p->o_tab[set];
+    a.twy = reinterpret_cast<const cplx<T>*>(t + tb.t_twy);
+    a.mky = reinterpret_cast<const cplx<T>*>(t + tb.t_mky);
+    a.rowoff = reinterpret_cast<const int*>(t + tb.t_rowoff);
+    a.lmax = reinterpret_cast<const int*>(t + tb.t_lmax);
+    a.elen = reinterpret_cast<const int*>(t + tb.t_elen);
+    a.wrows = reinterpret_cast<const cplx<T>*>(t + tb.t_wrows);
+    a.winf = reinterpret_cast<const cplx<T>*>(t + tb.t_winf);
+    a.wlast = reinterpret_cast<const cplx<T>*>(t + tb.t_wlast);
     a.zsolver = p->zsolver;
     a.bz0 = p->bz0;
     a.bz1 = p->bz1;
-    a.bmid = reinterpret_cast<const cplx<T>*>(t + p->t_bmid);
+    a.bmid = reinterpret_cast<const cplx<T>*>(t + tb.t_bmid);
     a.zper = (p->bz0 == pp::BC_P) ? 1 : 0;
     if (a.zper) {
-        a.aoff = reinterpret_cast<const int*>(t + p->t_aoff);
-        a.alen = reinterpret_cast<const int*>(t + p->t_alen);
-        a.aelen = reinterpret_cast<const int*>(t + p->t_aelen);
-        a.qelen = reinterpret_cast<const int*>(t + p->t_qelen);
-        a.arows = reinterpret_cast<const cplx<T>*>(t + p->t_arows);
-        a.qoff = reinterpret_cast<const int*>(t + p->t_qoff);
-        a.qlen = reinterpret_cast<const int*>(t + p->t_qlen);
-        a.qrows = reinterpret_cast<const cplx<T>*>(t + p->t_qrows);
-        a.qlast = reinterpret_cast<const cplx<T>*>(t + p->t_qlast);
-        a.inv_den = reinterpret_cast<const cplx<T>*>(t + p->t_invden);
-        a.inv_gamma = reinterpret_cast<const cplx<T>*>(t + p->t_invgam);
+        a.aoff = reinterpret_cast<const int*>(t + tb.t_aoff);
+        a.alen = reinterpret_cast<const int*>(t + tb.t_alen);
+        a.aelen = reinterpret_cast<const int*>(t + tb.t_aelen);
+        a.qelen = reinterpret_cast<const int*>(t + tb.t_qelen);
+        a.arows = reinterpret_cast<const cplx<T>*>(t + tb.t_arows);
+        a.qoff = reinterpret_cast<const int*>(t + tb.t_qoff);
+        a.qlen = reinterpret_cast<const int*>(t + tb.t_qlen);
+        a.qrows = reinterpret_cast<const cplx<T>*>(t + tb.t_qrows);
+        a.qlast = reinterpret_cast<const cplx<T>*>(t + tb.t_qlast);
+        a.inv_den = reinterpret_cast<const cplx<T>*>(t + tb.t_invden);
+        a.inv_gamma = reinterpret_cast<const cplx<T>*>(t + tb.t_invgam);
     }
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
     a.mu = sc + pp::SC_COUNT + 3 * p->batch;
@@ -623,7 +659,7 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
     const double npts = (double)p->nx * p->ny * p->nz;
     pp_status st;
     if ((st = mark(p, s, 0)) != PP_OK) return st;
-    PP_HIP((pp::launch_xfwd<T, Tio>(f, S, partial, xa, p->batch, faces, s)));
+    PP_HIP((pp::launch_xfwd<T, Tio, T>(f, S, partial, xa, p->batch, faces, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p, false), p->batch, npts,
                                     sc + pp::SC_COUNT + 3 * p->batch, sc + pp::SC_MAXF, s));
@@ -634,14 +670,49 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
     return mark(p, s, -1);
 }
 
+// z stage of a refined solve: the mixed march where it exists (the double
+// slots from their double spectra), else the float march.
+pp_status refined_mid(pp_plan p, unsigned char* ws, const pp::MidArgs<float>& ma, const pp::MidArgs<double>& ma64,
+                      hipStream_t s) {
+    cplx<float>* S = reinterpret_cast<cplx<float>*>(ws + p->o_S);
+    if (p->nlo > 0) {
+        const cplx<double>* Slo = reinterpret_cast<const cplx<double>*>(ws + p->o_lo);
+        PP_HIP(pp::launch_mid_mixed(Slo, S, ma64, ma, p->lo0, p->nlo, p->batch, s));
+    } else {
+        PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
+    }
+    return PP_OK;
+}
+
+// FP32 solves wrapped in iterative refinement with an FP64 residual and update.
+// Every solve transforms along x in double arithmetic and keeps the spectra of
+// the slots of the smallest x wavenumbers in double (set_mixed_slots); the
+// rest of the solve runs in float.  The first solution u0 is kept in float (it
+// is a float solve's result); the first correction reads it and writes u in
+// double; any further correction updates u in place.
 pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, hipStream_t s, bool project,
                       bool demean, const pp::FaceArgs<double>* faces) {
-    pp::XArgs<float> xa = make_xargs<float>(p, ws);
-    pp::MidArgs<float> ma = make_midargs<float>(p, ws, project, demean);
+    pp::XArgs<double> xa64 = make_xargs<double>(p, ws, 1);   // forward: double arithmetic, split store
+    xa64.lo0 = p->lo0;
+    xa64.nlo = p->nlo;
+    xa64.slo = reinterpret_cast<cplx<double>*>(ws + p->o_lo);
+    pp::XArgs<float> xa = make_xargs<float>(p, ws, 0);       // inverse: float
+    pp::MidArgs<float> ma = make_midargs<float>(p, ws, project, demean, 0);
+    pp::MidArgs<double> ma64 = make_midargs<double>(p, ws, project, demean, 1);
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
     double* partial = reinterpret_cast<double*>(ws + p->o_partial);
     cplx<float>* S = reinterpret_cast<cplx<float>*>(ws + p->o_S);
-    float* r = reinterpret_cast<float*>(ws + p->o_r);
+    float* u0 = reinterpret_cast<float*>(ws + p->o_u0);   // first solution
+    // the residual of the first correction is formed inside the forward x
+    // transform (rows up to 512); otherwise it is stored, in double: a float
+    // residual rounds the part the first solution's float rounding puts into it,
+    // which is large where one direction is much finer than the others, and the
+    // float solve of that rounding limits the correction (to ~1e-5 of its size
+    // on 8 x 8 x 512 and 8 x 16 x 1024 grids, against ~3e-7 here).  Later
+    // corrections (rare) form a float residual in u0's array.
+    const bool fused = pp::res_fused_supported(p->nx);
+    double* r64 = reinterpret_cast<double*>(ws + p->o_r);
+    float* r32 = u0;
     const size_t n = (size_t)p->nx * p->ny * p->nz;
     const double npts = (double)n;
     // gauge region whose mean is held fixed across corrections:
@@ -666,36 +737,59 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         ra.faces = *faces;
         ra.has_faces = 1;
     }
+    const bool keep_u0 = p->ir_max > 0;   // with no correction the float solve goes straight to u
 
     pp_status st;
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_ir_init(sc, p->batch, s));
     if ((st = mark(p, s, 0)) != PP_OK) return st;
-    PP_HIP((pp::launch_xfwd<float, double>(f, S, partial, xa, p->batch, faces, s)));
+    PP_HIP((pp::launch_xfwd<double, double, float>(f, S, partial, xa64, p->batch, faces, s)));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p, false), p->batch, npts, sc + pp::SC_COUNT + 3 * p->batch,
                                     sc + pp::SC_MAXF, s));
     if ((st = mark(p, s, 1)) != PP_OK) return st;
-    PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
+    if ((st = refined_mid(p, ws, ma, ma64, s)) != PP_OK) return st;
     ma.mu = sc + pp::SC_COUNT;   // corrections project their own right-hand side
+    ma64.mu = sc + pp::SC_COUNT;
     if ((st = mark(p, s, 2)) != PP_OK) return st;
-    PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 0, s));
+    if (keep_u0) PP_HIP(pp::launch_xinv_first(S, u0, xa, p->batch, sc, region, partial, s));
+    else PP_HIP(pp::launch_xinv_update(S, u, nullptr, xa, p->batch, sc, region, partial, pp::XINV_FIRST, s));
     if ((st = mark(p, s, 3)) != PP_OK) return st;
     PP_HIP(pp::launch_finalize_update(partial, x_records(p, true), p->batch, nregion, sc, 1, s));
     if ((st = mark(p, s, -1)) != PP_OK) return st;
     p->last_iters = 0;
     p->last_rel = 1.0;
     for (int it = 1; it <= p->ir_max; ++it) {
-        if ((st = mark(p, s, 3)) != PP_OK) return st;
-        PP_HIP(pp::launch_residual(f, u, r, ra, sc, s));
-        if ((st = mark(p, s, 0)) != PP_OK) return st;
-        PP_HIP((pp::launch_xfwd<float, float>(r, S, partial, xa, p->batch, nullptr, s)));
+        if (fused && it == 1) {
+            pp::XArgs<double> xr = xa64;
+            xr.u0 = u0;
+            xr.sc = sc;
+            for (int i = 0; i < 6; ++i) xr.fbc[i] = ra.bc[i];
+            xr.proj = ra.proj;
+            xr.ihx2 = ra.ihx2;
+            xr.ihy2 = ra.ihy2;
+            xr.ihz2 = ra.ihz2;
+            if ((st = mark(p, s, 0)) != PP_OK) return st;
+            PP_HIP(pp::launch_xfwd_res(f, S, partial, xr, p->batch, faces, s));
+        } else if (fused) {
+            if ((st = mark(p, s, 3)) != PP_OK) return st;
+            PP_HIP((pp::launch_residual<double, float>(f, u, r32, ra, sc, s)));
+            if ((st = mark(p, s, 0)) != PP_OK) return st;
+            PP_HIP((pp::launch_xfwd<double, float, float>(r32, S, partial, xa64, p->batch, nullptr, s)));
+        } else {
+            if ((st = mark(p, s, 3)) != PP_OK) return st;
+            if (it == 1) PP_HIP((pp::launch_residual<float, double>(f, u0, r64, ra, sc, s)));
+            else PP_HIP((pp::launch_residual<double, double>(f, u, r64, ra, sc, s)));
+            if ((st = mark(p, s, 0)) != PP_OK) return st;
+            PP_HIP((pp::launch_xfwd<double, double, float>(r64, S, partial, xa64, p->batch, nullptr, s)));
+        }
         if ((st = mark(p, s, 3)) != PP_OK) return st;
         PP_HIP(pp::launch_finalize_xfwd(partial, x_records(p, false), p->batch, npts, sc + pp::SC_COUNT, nullptr, s));
         if ((st = mark(p, s, 1)) != PP_OK) return st;
-        PP_HIP(pp::launch_mid<float>(S, ma, p->batch, s));
+        if ((st = refined_mid(p, ws, ma, ma64, s)) != PP_OK) return st;
         if ((st = mark(p, s, 2)) != PP_OK) return st;
-        PP_HIP(pp::launch_xinv_update(S, u, xa, p->batch, sc, region, partial, 1, s));
+        PP_HIP(pp::launch_xinv_update(S, u, it == 1 ? u0 : nullptr, xa, p->batch, sc, region, partial,
+                                      pp::XINV_UPDATE, s));
         if ((st = mark(p, s, 3)) != PP_OK) return st;
         PP_HIP(pp::launch_finalize_update(partial, x_records(p, true), p->batch, nregion, sc, 0, s));
         if ((st = mark(p, s, -1)) != PP_OK) return st;
@@ -707,11 +801,12 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
         p->last_rel = rel;
         if ((st = collect(p)) != PP_OK) return st;
         if (!std::isfinite(maxf) || !std::isfinite(rel)) return PP_ERR_NONFINITE;
-        // estimated error after this correction: the next correction, predicted
-        // from the contraction of the last two corrections.  The first correction
-        // has no predecessor (the ratio to the first solution says nothing about
-        // how fast corrections of a residual contract), so it must itself be small.
-        const double rho = (it >= 2 && relprev > 0.0) ? std::min(1.0, rel / relprev) : 1.0;
+        // estimated error after this correction: the next correction, the size
+        // of this one times the contraction factor.  After two corrections the
+        // factor is their ratio; after the first it is the first correction
+        // itself, the relative error of the first solve, which the correction's
+        // own solve (the same float solve) is taken to repeat.
+        const double rho = (it >= 2 && relprev > 0.0) ? std::min(1.0, rel / relprev) : std::min(1.0, rel);
         if (rel == 0.0 || rel * rho <= p->ir_tol) return PP_OK;
     }
     return PP_ERR_NOT_CONVERGED;
@@ -768,7 +863,9 @@ pp_status dispatch(pp_plan p, const void* f, void* u, void* workspace, void* str
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
     if (!tables_present(p, workspace)) {
-        PP_HIP(hipMemcpyAsync(ws + p->o_tables, p->blob.data(), p->blob.size(), hipMemcpyHostToDevice, s));
+        for (int i = 0; i < p->ntab; ++i)
+            PP_HIP(hipMemcpyAsync(ws + p->o_tab[i], p->tb[i].blob.data(), p->tb[i].blob.size(), hipMemcpyHostToDevice,
+                                  s));
         tables_uploaded(p, workspace);
     }
     // zero-mode treatment; the adjoint trades projection and mean shift
@@ -870,7 +967,9 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         while (lines > 1 && (size_t)((nx + 1) / 2) * lines > (size_t)pp::kXThreads * (pp::xdir_rmax(nx) / 2)) --lines;
         // LDS: the lines plus two twiddle tables of nx; fewer lines to keep two
         // workgroups per CU, and a single line may use the whole LDS
-        auto xlds = [&](int l) { return ((size_t)l * pp::padded_len(nx) + 2 * (size_t)nx) * p->elem; };
+        // (the refined solve's forward x transform works in double)
+        const size_t xelem = (dtype == PP_F32) ? sizeof(cplx<float>) : sizeof(cplx<double>);
+        auto xlds = [&](int l) { return ((size_t)l * pp::padded_len(nx) + 2 * (size_t)nx) * xelem; };
         const int lines_all = lines;
         while (lines > 1 && xlds(lines) > (size_t)pp::kXLdsBytes) --lines;
         // except for the exact-count shape (one line of 64 rmax values per
@@ -898,8 +997,13 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     // partial records per batch entry: one per (workgroup, wavefront) of the persistent
     // x kernels, whose grid never exceeds the row blocks of all batch entries
     p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz * batch * pp::kXWaves;
-    if (f64) build_tables<double>(p);
-    else build_tables<float>(p);
+    if (f64) build_tables<double>(p, p->tb[0]);
+    else build_tables<float>(p, p->tb[0]);
+    if (dtype == PP_F32_REFINED) {
+        build_tables<double>(p, p->tb[1]);
+        p->ntab = 2;
+        set_mixed_slots(p);
+    }
 
     const size_t n = (size_t)nx * ny * nz;
     size_t off = 0;
@@ -907,12 +1011,18 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     off = align_up(off + sizeof(double) * (pp::SC_COUNT + 4 * (size_t)batch));
     p->o_partial = off;
     off = align_up(off + sizeof(double) * 3 * p->nper * batch);
-    p->o_tables = off;
-    off = align_up(off + p->blob.size());
+    for (int i = 0; i < p->ntab; ++i) {
+        p->o_tab[i] = off;
+        off = align_up(off + p->tb[i].blob.size());
+    }
     p->o_S = off;
     off = align_up(off + p->elem * (size_t)batch * p->slots * nz * ny);
-    p->o_r = off;
+    p->o_r = off;   // refined, rows over 512: the double residual
+    if (dtype == PP_F32_REFINED && !pp::res_fused_supported(nx)) off = align_up(off + sizeof(double) * n * batch);
+    p->o_u0 = off;
     if (dtype == PP_F32_REFINED) off = align_up(off + sizeof(float) * n * batch);
+    p->o_lo = off;
+    off = align_up(off + sizeof(cplx<double>) * (size_t)batch * p->nlo * nz * ny);
     p->ws_bytes = off;
     *out = p;
     return PP_OK;
@@ -932,6 +1042,7 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver) {
         if (p->nz > 512 || p->ny > 512) return PP_ERR_SIZE;
     }
     p->zsolver = (int)solver;
+    if (p->dtype == PP_F32_REFINED) set_mixed_slots(p);
     return PP_OK;
 }
 

@@ -64,6 +64,12 @@ template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) 
     return r;
 }
 
+// Complex value in another precision.
+template <typename To, typename V> __device__ __forceinline__ cplx<To> cvt(const V& v) {
+    if constexpr (std::is_same_v<V, cplx<To>>) return v;
+    else return mk<To>((To)v.x, (To)v.y);
+}
+
 // Multiply by -i (forward transforms) or +i (inverse transforms).
 template <bool INV, typename V> __device__ __forceinline__ V rot(V a) {
     V r;

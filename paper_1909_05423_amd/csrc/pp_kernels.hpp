@@ -50,6 +50,18 @@ template <typename T> struct XArgs {
     FftDesc fx;              // radix plan for nx
     const cplx<T>* twx;      // FFT twiddles of length nx, packed by stage (wfft_stage)
     const cplx<T>* mkx;      // exp(-i pi k / (2 nx)), k < nx
+    // split store of the forward kernel (double arithmetic, float spectra): slots
+    // lo0 .. lo0+nlo-1 go to the double array slo [b][z][k][y] instead
+    int lo0, nlo;
+    cplx<double>* slo;
+    // fused refinement residual (forward kernel with RES): the rows transformed
+    // are r = f - lift - c - L_h u0 (double arithmetic; c as in ResidualArgs),
+    // and the spectra are stored scaled by sc[SC_SCALE]
+    const float* u0;
+    const double* sc;
+    int fbc[6];              // face types (Bc), x-, x+, y-, y+, z-, z+
+    int proj;
+    double ihx2, ihy2, ihz2;
 };
 
 // Non-homogeneous face values, faces in the order x-, x+, y-, y+, z-, z+.  The
@@ -151,23 +163,43 @@ int x_grid(int nblocks);
 int x_launch_grid(int nblocks, bool paired);
 
 // faces: null, or the face values to lift into the source as it is read.
-template <typename T, typename Tin>
-hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+// T: arithmetic; Tin: source; Ts: spectra (T, or float with the double slots of XArgs::slo).
+template <typename T, typename Tin, typename Ts>
+hipError_t launch_xfwd(const Tin* f, cplx<Ts>* S, double* partial, const XArgs<T>& a, int batch,
                        const FaceArgs<Tin>* faces, hipStream_t s);
+// The forward transform of the refinement residual r = f - lift - c - L_h u0
+// (XArgs::u0, sc, fbc, proj, ih*2), computed as the rows are read: double
+// arithmetic, float spectra with the double slots.  Rows of at most 512
+// (res_fused_supported); other shapes take launch_residual + launch_xfwd.
+bool res_fused_supported(int nx);
+hipError_t launch_xfwd_res(const double* f, cplx<float>* S, double* partial, const XArgs<double>& a, int batch,
+                           const FaceArgs<double>* faces, hipStream_t s);
 
 template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
                        hipStream_t s);
 
-// Refinement update: u = (accumulate ? u : 0) + d / scale - gauge_shift[b];
-// partials (sum over the gauge region of the new u, max |d / scale|, max |u_new|)
-// per wavefront.
-hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float>& a, int batch,
-                              const double* scalars, int gauge_region, double* partial, int accumulate,
-                              hipStream_t s);
+// Refinement updates, with partials (sum over the gauge region of the new u,
+// max |d / scale|, max |u_new|) per wavefront.
+//   launch_xinv_first:  u0 = d / scale, stored in float (the first solve; its
+//                       float values unshifted, so the store rounds nothing);
+//   launch_xinv_update: mode XINV_FIRST: u = d / scale - cmean (double);
+//                       XINV_UPDATE: u = prev + d / scale - cmean - gauge_shift[b],
+//                       prev = uprev (float) when given, else u itself.
+hipError_t launch_xinv_first(const cplx<float>* S, float* u0, const XArgs<float>& a, int batch, const double* scalars,
+                             int gauge_region, double* partial, hipStream_t s);
+hipError_t launch_xinv_update(const cplx<float>* S, double* u, const float* uprev, const XArgs<float>& a, int batch,
+                              const double* scalars, int gauge_region, double* partial, int mode, hipStream_t s);
 
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);
+
+// The refined solve's z stage: slots lo0 .. lo0+nlo-1 from their double
+// spectra Slo in double (tables of ad), the rest in float (tables of af); every
+// result in float in S.  Supported where mixed_march_supported().
+bool mixed_march_supported(int ny, int zsolver);
+hipError_t launch_mid_mixed(const cplx<double>* Slo, cplx<float>* S, const MidArgs<double>& ad,
+                            const MidArgs<float>& af, int lo0, int nlo, int batch, hipStream_t s);
 
 // The same stage with the z-systems solved by parallel cyclic reduction
 // (y transforms as separate passes; nz <= 512, ny <= 512, z not periodic).
@@ -183,7 +215,8 @@ hipError_t launch_finalize_xfwd(const double* partial, int nper, int batch, doub
 hipError_t launch_finalize_update(const double* partial, int nper, int batch, double nregion, double* scalars,
                                   int first, hipStream_t s);
 
-hipError_t launch_residual(const double* f, const double* u, float* r, const ResidualArgs& a,
+template <typename Tu, typename Tr>
+hipError_t launch_residual(const double* f, const Tu* u, Tr* r, const ResidualArgs& a,
                            const double* scalars, hipStream_t s);
 
 // Initial scalars of the refinement loop (unit scale, no gauge shift).

@@ -23,6 +23,8 @@
 // Writing columns with y contiguous is the x <-> y transpose, done through LDS
 // so that both the row reads and the column writes are coalesced.
 
+#include <type_traits>
+
 #include "pp_kernels.hpp"
 
 namespace pp {
@@ -108,15 +110,24 @@ template <typename T> __device__ __forceinline__ void put_spec(cplx<T>* p, const
 // 1024 x 1024 x 512) and for the double kernel on rows of 512 without face
 // values (4 registers over the budget of two waves); no constraint elsewhere
 // (the other kernels with double data spill under it).
-template <typename T, typename Tin, int RMAX, bool FACES>
+// The general form of the fused residual (RES) keeps no such constraint: it
+// spills under it.
+template <typename T, typename Tin, int RMAX, bool FACES, bool FULL = true, bool RES = false>
 constexpr int kXfwdMinWaves =
-    ((sizeof(T) == 4 && sizeof(Tin) == 4) || (sizeof(T) == 8 && RMAX == 8 && !FACES)) ? 2 : 1;
+    (RES && !FULL) ? 1 : ((sizeof(T) == 4 && sizeof(Tin) == 4) || (sizeof(T) == 8 && RMAX == 8 && !FACES)) ? 2 : 1;
 
-template <typename T, typename Tin, int NTH, int RMAX, bool FULL, bool FACES>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWaves<T, Tin, RMAX, FACES>))) void k_xfwd(const Tin* __restrict__ f, cplx<T>* __restrict__ S,
+// RES: the fused refinement residual (XArgs::u0 ...): besides the source
+// rows, each lane fetches its own u0 values of the two rows, of the rows
+// outside the pair in y and of the neighbouring planes; the x neighbours come
+// from the adjacent lanes (exact-count form) or from loads (general form).
+// Neighbours past a face are read at a valid address (the periodic image, or
+// the cell itself with the sign of the ghost rule) as in k_residual.
+template <typename T, typename Tin, typename Ts, int NTH, int RMAX, bool FULL, bool FACES, bool RES = false>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWaves<T, Tin, RMAX, FACES, FULL, RES>))) void k_xfwd(const Tin* __restrict__ f, cplx<Ts>* __restrict__ S,
                                               double* __restrict__ partial, XArgs<T> a, int nblocks,
                                               FaceArgs<Tin> fa) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool SPLIT = !std::is_same_v<T, Ts>;   // double arithmetic, float spectra + double slots
     constexpr int NW = NTH / 64;
     constexpr int PAIRS = RMAX / 2;   // FULL: column writes per thread, slots * nlines == NTH * PAIRS
     const int nx = FULL ? 64 * RMAX : a.nx;
@@ -137,11 +148,26 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
     // periodic rows of 512, double spectra: the transform's first stage runs
     // on the row registers (w512_first; in float the extra registers cost more
     // occupancy than the LDS round trip saves)
-    constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8;
+    // (not with the fused residual, whose neighbour values need the registers)
+    constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8 && !RES;
     const bool reg512 = R512 && a.bx == BC_P;
 
     // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
     Tin ra[RMAX], rb[RMAX];
+    // RES: u0 at the two rows (ua, ub), at the row below a and above b (uya, uyb)
+    // and at the planes below and above (uza0, uza1, uzb0, uzb1)
+    constexpr int RR = RES ? RMAX : 1;
+    float ua[RR], ub[RR], uya[RR], uyb[RR], uza0[RR], uza1[RR], uzb0[RR], uzb1[RR];
+    // neighbour row / plane index past a face: the periodic image or the cell itself
+    auto nb_idx = [&](int i, int n_, int dir, int kind) -> int {
+        const int q = i + dir;
+        if (q >= 0 && q < n_) return q;
+        return kind == BC_P ? (q < 0 ? n_ - 1 : 0) : i;
+    };
+    auto nb_sgn = [&](int i, int n_, int dir, int kind) -> double {
+        const int q = i + dir;
+        return (q >= 0 && q < n_) || kind != BC_D ? 1.0 : -1.0;
+    };
     // FULL with face values: the x-face values of this wave's two rows, fetched
     // with them (the lanes holding columns 0 and nx-1 use them)
     Tin gx[FACES && FULL ? 4 : 1];
@@ -171,6 +197,63 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                     if (ya + 1 < ny) rb[r] = ld_stream(src + (size_t)(ya + 1) * nx + n);
                 }
             }
+            if constexpr (RES) {
+                // the pair's own u0 values travel with the source rows; the
+                // neighbour rows are read when the block is formed (fetch_nb)
+                const float* up = a.u0 + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+                const bool va = FULL || (j < nlines && n < nx && ya < ny);
+                const bool vb = FULL || (j < nlines && n < nx && ya + 1 < ny);
+                ua[r] = va ? up[(size_t)ya * nx + n] : 0.f;
+                ub[r] = vb ? up[(size_t)(ya + 1) * nx + n] : 0.f;
+            }
+        }
+    };
+    // RES: u0 of the rows outside the pair in y (below a; above b, or above a
+    // when b is past the end) and of the neighbouring planes, for block blk
+    auto fetch_nb = [&](int blk) {
+        if constexpr (RES) {
+            const XBlock xb = x_block(blk, nyb, nz, ty);
+            const float* up = a.u0 + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+            const long plane = (long)ny * nx;
+            const long zm = (long)(nb_idx(xb.z, nz, -1, a.fbc[4]) - xb.z) * plane;
+            const long zp = (long)(nb_idx(xb.z, nz, 1, a.fbc[5]) - xb.z) * plane;
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                const int p = FULL ? 0 : fdiv(r, inv_epl);
+                const int j = wave + NW * p, n = lane + 64 * (r - p * epl);
+                const int ya = xb.y0 + 2 * j;
+                const bool va = FULL || (j < nlines && n < nx && ya < ny);
+                const bool vb = FULL || (j < nlines && n < nx && ya + 1 < ny);
+                const int ym = nb_idx(ya, ny, -1, a.fbc[2]);
+                const int yp = nb_idx(vb ? ya + 1 : ya, ny, 1, a.fbc[3]);
+                const float* pa = up + (size_t)(va ? ya : 0) * nx + (va ? n : 0);
+                const float* pb = up + (size_t)(vb ? ya + 1 : 0) * nx + (vb ? n : 0);
+                uya[r] = va ? up[(size_t)ym * nx + n] : 0.f;
+                uyb[r] = va ? up[(size_t)yp * nx + n] : 0.f;
+                uza0[r] = va ? pa[zm] : 0.f;
+                uza1[r] = va ? pa[zp] : 0.f;
+                uzb0[r] = vb ? pb[zm] : 0.f;
+                uzb1[r] = vb ? pb[zp] : 0.f;
+            }
+        }
+    };
+    // RES: the value of u0 at column n - 1 (dir -1) or n + 1 (dir +1) of the row
+    // held in c (exact-count form: lane l holds columns l + 64 r), from the
+    // adjacent lane; past the x faces the periodic image or the ghost rule
+    auto xnb = [&](const float (&c)[RR], int r, int dir) -> double {
+        if constexpr (RES && FULL) {
+            const int src = (lane + dir) & 63;
+            const int rw = (r + dir + RMAX) % RMAX;   // the register of the wrapped-around lane
+            const float t1 = __shfl(c[r], src, 64);
+            const float t2 = __shfl(c[rw], src, 64);
+            const bool wrap = dir < 0 ? (lane == 0) : (lane == 63);
+            const int n = lane + 64 * r;
+            const bool face = dir < 0 ? (n == 0) : (n == nx - 1);
+            const int kind = a.fbc[dir < 0 ? 0 : 1];
+            if (face && kind != BC_P) return (kind == BC_D ? -1.0 : 1.0) * (double)c[r];
+            return (double)(wrap ? t2 : t1);
+        } else {
+            return 0.0;
         }
     };
     // per-wavefront sums of the source, one record per (batch entry, workgroup, wavefront)
@@ -185,8 +268,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
     }
     double acc = 0.0, amax = 0.0;
     int cur_b = -1;
+    // RES: the residual's spectra and sums are scaled by a power of two (exact)
+    double rscale = 1.0;
+    if constexpr (RES) rscale = a.sc[SC_SCALE];
     auto flush = [&]() {
-        const double s_ = wave_sum(acc), m_ = wave_max(amax);
+        const double s_ = wave_sum(acc) * rscale, m_ = wave_max(amax) * rscale;
         if (lane == 0 && cur_b >= 0) {
             const size_t rec = cur_b * rec_per_batch + (size_t)blockIdx.x * NW + wave;
             partial[2 * rec] = s_;
@@ -228,6 +314,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
             flush();
             cur_b = xb.b;
         }
+        fetch_nb(blk);
         lds_barrier();   // the previous column writes are done reading the lines (and the twiddles are in)
         cplx<T> vf[R512 ? 8 : 1];   // periodic rows of 512: the packed line stays in registers
         // 1. registers -> own packed lines (row 2j real part, row 2j+1 imaginary part),
@@ -249,7 +336,44 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                         lb += fa.c[1] * (double)gx[3];
                     }
                 }
-                const double fa_ = (double)ra[r] - la, fb_ = (double)rb[r] - lb;
+                double fa_ = (double)ra[r] - la, fb_ = (double)rb[r] - lb;
+                if constexpr (RES) {
+                    // r = f - lift - c - L_h u0; second differences as sums of first
+                    // differences (as in k_residual)
+                    const int ya = xb.y0 + 2 * j;
+                    const bool va = FULL || ya < ny, vb = FULL || ya + 1 < ny;
+                    const double ca = ua[r], cb = ub[r];
+                    double xam, xap, xbm, xbp;
+                    if constexpr (FULL) {
+                        xam = xnb(ua, r, -1);
+                        xap = xnb(ua, r, 1);
+                        xbm = xnb(ub, r, -1);
+                        xbp = xnb(ub, r, 1);
+                    } else {
+                        const float* up = a.u0 + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+                        const float* ra_ = up + (size_t)(va ? ya : 0) * nx;
+                        const float* rb_ = up + (size_t)(vb ? ya + 1 : 0) * nx;
+                        const int qm = nb_idx(n, nx, -1, a.fbc[0]), qp = nb_idx(n, nx, 1, a.fbc[1]);
+                        const double sm = nb_sgn(n, nx, -1, a.fbc[0]), sp = nb_sgn(n, nx, 1, a.fbc[1]);
+                        xam = va ? sm * (double)ra_[qm] : 0.0;
+                        xap = va ? sp * (double)ra_[qp] : 0.0;
+                        xbm = vb ? sm * (double)rb_[qm] : 0.0;
+                        xbp = vb ? sp * (double)rb_[qp] : 0.0;
+                    }
+                    const double ya_dn = nb_sgn(ya, ny, -1, a.fbc[2]) * (double)uya[r];
+                    const double ya_up = vb ? cb : nb_sgn(ya, ny, 1, a.fbc[3]) * (double)uyb[r];
+                    const double yb_up = nb_sgn(ya + 1, ny, 1, a.fbc[3]) * (double)uyb[r];
+                    const double sz0 = nb_sgn(xb.z, nz, -1, a.fbc[4]), sz1 = nb_sgn(xb.z, nz, 1, a.fbc[5]);
+                    const double lapa = ((xam - ca) + (xap - ca)) * a.ihx2 + ((ya_dn - ca) + (ya_up - ca)) * a.ihy2 +
+                                        ((sz0 * (double)uza0[r] - ca) + (sz1 * (double)uza1[r] - ca)) * a.ihz2;
+                    const double lapb = ((xbm - cb) + (xbp - cb)) * a.ihx2 + ((ca - cb) + (yb_up - cb)) * a.ihy2 +
+                                        ((sz0 * (double)uzb0[r] - cb) + (sz1 * (double)uzb1[r] - cb)) * a.ihz2;
+                    double c0 = 0.0;
+                    if (a.proj == 1) c0 = a.sc[SC_COUNT + 3 * batch + xb.b];
+                    else if (a.proj == 2 && xb.z == 0) c0 = (double)nz * a.sc[SC_COUNT + 3 * batch + xb.b];
+                    fa_ = va ? fa_ - c0 - lapa : 0.0;
+                    fb_ = vb ? fb_ - c0 - lapb : 0.0;
+                }
                 acc += fa_ + fb_;
                 amax = nmax(amax, nmax(fabs(fa_), fabs(fb_)));
                 T va = (T)fa_, vb = (T)fb_;
@@ -347,7 +471,19 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
         lds_barrier();
 
         // 3. post-process and write columns (y contiguous); one thread per (slot, row pair)
-        cplx<T>* dstS = S + (size_t)xb.b * a.slots * nz * ny;
+        cplx<Ts>* dstS = S + (size_t)xb.b * a.slots * nz * ny;
+        // split store: the slots of the double array take their values unrounded
+        auto store = [&](int m, int y, cplx<T> v) {
+            if constexpr (RES) v = cscale(v, (T)rscale);
+            if constexpr (SPLIT) {
+                const int k = m - a.lo0;
+                if (k >= 0 && k < a.nlo) {
+                    a.slo[(((size_t)xb.b * nz + xb.z) * a.nlo + k) * ny + y] = cvt<double>(v);
+                    return;
+                }
+            }
+            put_spec<Ts>(dstS + (size_t)m * a.sstride + (size_t)xb.z * a.zstride + y, cvt<Ts>(v));
+        };
         if (FULL) {
 #pragma unroll
             for (int q = 0; q < PAIRS; ++q) {
@@ -356,9 +492,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                 const int ya = xb.y0 + 2 * j;
                 cplx<T> oa, ob;
                 column(m, j, oa, ob);
-                const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
-                put_spec<T>(dstS + col + ya, oa);
-                put_spec<T>(dstS + col + ya + 1, ob);
+                store(m, ya, oa);
+                store(m, ya + 1, ob);
             }
         } else {
             for (int i = tid; i < a.slots * nlines; i += NTH) {
@@ -366,9 +501,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                 const int ya = xb.y0 + 2 * j, yb = ya + 1;
                 cplx<T> oa, ob;
                 column(m, j, oa, ob);
-                const size_t col = (size_t)m * a.sstride + (size_t)xb.z * a.zstride;
-                if (ya < ny) put_spec<T>(dstS + col + ya, oa);
-                if (yb < ny) put_spec<T>(dstS + col + yb, ob);
+                if (ya < ny) store(m, ya, oa);
+                if (yb < ny) store(m, yb, ob);
             }
         }
     };
@@ -392,11 +526,15 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
 // MODE XINV_STORE writes u = x - shift[b]; XINV_UPDATE adds the scaled
 // correction to a double u and XINV_FIRST stores it without reading u; both
 // write per-wavefront partials (sum over the gauge region, max |d|, max |u|).
-template <typename T, typename Tout, int NTH, int MODE, int RMAX, bool FULL>
-__global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tout* __restrict__ u, XArgs<T> a,
+// Tp: type of the previous solution an update adds to (Tout: u itself, in
+// place; float: the separate array uprev holding the first float solution).
+template <typename T, typename Tout, typename Tp, int NTH, int MODE, int RMAX, bool FULL>
+__global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tout* __restrict__ u,
+                                              const Tp* __restrict__ uprev, XArgs<T> a,
                                               const double* __restrict__ shift, const double* __restrict__ scalars,
                                               int gauge_region, double* __restrict__ partial, int nblocks) {
-    constexpr bool UPD = (MODE != XINV_STORE);   // refinement update (partials, double output)
+    constexpr bool UPD = (MODE != XINV_STORE);   // refinement update (partials)
+    constexpr bool INPLACE = std::is_same_v<Tp, Tout>;
     // rows of 512, double spectra: w512_* stages when x is periodic (in float
     // the extra registers cost more occupancy than the LDS round trip saves)
     constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8;
@@ -488,6 +626,9 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
             cur_b = xb.b;
         }
         Tout* dst = u + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
+        const Tp* prv = nullptr;
+        if constexpr (INPLACE) prv = dst;
+        else prv = uprev + ((size_t)xb.b * nz + xb.z) * (size_t)ny * nx;
         lds_barrier();   // the previous inverse transforms are done with the lines (and the twiddles are in)
         // 1. registers -> packed complex spectra of row pairs (any line)
 #pragma unroll
@@ -516,7 +657,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
             for (int k = 0; k < RMAX; ++k)
 #pragma unroll
                 for (int part = 0; part < 2; ++part)
-                    uo[2 * k + part] = (double)dst[(size_t)(xb.y0 + 2 * wave + part) * nx + lane + 64 * k];
+                    uo[2 * k + part] = (double)prv[(size_t)(xb.y0 + 2 * wave + part) * nx + lane + 64 * k];
         }
         // the next block's spectra (past the end: this block's again, unused)
         const int nxt = x_next_block<sizeof(T) == 4>(blk);   // pairs in float (x_next_block)
@@ -578,7 +719,8 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                             st_stream(dst + idx, (Tout)((double)v - sh));
                         } else {
                             const double d = ((double)v - sh) * inv_scale;
-                            const double un = uo[UR > 1 ? 2 * k + part : 0] + d - gshift;   // uo = 0 for XINV_FIRST
+                            // uo = 0 for XINV_FIRST; sums and maxima of the stored value
+                            const double un = (double)(Tout)(uo[UR > 1 ? 2 * k + part : 0] + d - gshift);
                             st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
                             dmax = nmax(dmax, fabs(d));
@@ -602,7 +744,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                             st_stream(dst + idx, (Tout)((double)v - sh));
                         } else {
                             const double d = ((double)v - sh) * inv_scale;
-                            const double un = (MODE == XINV_UPDATE ? (double)dst[idx] : 0.0) + d - gshift;
+                            const double un = (double)(Tout)((MODE == XINV_UPDATE ? (double)prv[idx] : 0.0) + d - gshift);
                             st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
                             dmax = nmax(dmax, fabs(d));
@@ -657,102 +799,135 @@ template <int RMAX, typename T> static bool x_full(const XArgs<T>& a) {
     return RMAX <= 16 && a.nx == 64 * RMAX && a.ty == 2 * kXWaves && a.ny % a.ty == 0;
 }
 
-template <typename T, typename Tin, int RMAX, bool FACES>
-static hipError_t launch_xfwd_shape(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+template <typename T, typename Tin, typename Ts, int RMAX, bool FACES, bool RES = false>
+static hipError_t launch_xfwd_shape(const Tin* f, cplx<Ts>* S, double* partial, const XArgs<T>& a, int batch,
                                     const FaceArgs<Tin>& fa, hipStream_t s) {
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
     if constexpr (RMAX <= 16) {
         if (x_full<RMAX>(a)) {
-            allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, true, FACES>>();
-            hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, true, FACES>), dim3(x_launch_grid(nb, false)), dim3(kXThreads),
-                               x_lds_bytes(a), s, f, S, partial, a, nb, fa);
+            allow_lds<k_xfwd<T, Tin, Ts, kXThreads, RMAX, true, FACES, RES>>();
+            hipLaunchKernelGGL((k_xfwd<T, Tin, Ts, kXThreads, RMAX, true, FACES, RES>),
+                               dim3(x_launch_grid(nb, false)), dim3(kXThreads), x_lds_bytes(a), s, f, S, partial, a,
+                               nb, fa);
             return hipGetLastError();
         }
     }
     {
-        allow_lds<k_xfwd<T, Tin, kXThreads, RMAX, false, FACES>>();
-        hipLaunchKernelGGL((k_xfwd<T, Tin, kXThreads, RMAX, false, FACES>), dim3(x_launch_grid(nb, false)), dim3(kXThreads),
-                           x_lds_bytes(a), s, f, S, partial, a, nb, fa);
+        allow_lds<k_xfwd<T, Tin, Ts, kXThreads, RMAX, false, FACES, RES>>();
+        hipLaunchKernelGGL((k_xfwd<T, Tin, Ts, kXThreads, RMAX, false, FACES, RES>), dim3(x_launch_grid(nb, false)),
+                           dim3(kXThreads), x_lds_bytes(a), s, f, S, partial, a, nb, fa);
     }
     return hipGetLastError();
 }
 
-template <typename T, typename Tin, bool FACES>
-static hipError_t launch_xfwd_any(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+bool res_fused_supported(int nx) { return nx <= 512; }
+
+hipError_t launch_xfwd_res(const double* f, cplx<float>* S, double* partial, const XArgs<double>& a, int batch,
+                           const FaceArgs<double>* faces, hipStream_t s) {
+    if (a.nx > 512) return hipErrorInvalidValue;
+    const FaceArgs<double> none{};
+    if (faces) {
+        if (a.nx == 384) return launch_xfwd_shape<double, double, float, 6, true, true>(f, S, partial, a, batch, *faces, s);
+        return launch_xfwd_shape<double, double, float, 8, true, true>(f, S, partial, a, batch, *faces, s);
+    }
+    if (a.nx == 384) return launch_xfwd_shape<double, double, float, 6, false, true>(f, S, partial, a, batch, none, s);
+    return launch_xfwd_shape<double, double, float, 8, false, true>(f, S, partial, a, batch, none, s);
+}
+
+template <typename T, typename Tin, typename Ts, bool FACES>
+static hipError_t launch_xfwd_any(const Tin* f, cplx<Ts>* S, double* partial, const XArgs<T>& a, int batch,
                                   const FaceArgs<Tin>& fa, hipStream_t s) {
     // rows of 384 = 64 x 6: exact-count form with six values per lane
-    if (a.nx == 384) return launch_xfwd_shape<T, Tin, 6, FACES>(f, S, partial, a, batch, fa, s);
-    if (a.nx <= 512) return launch_xfwd_shape<T, Tin, 8, FACES>(f, S, partial, a, batch, fa, s);
-    if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, 16, FACES>(f, S, partial, a, batch, fa, s);
-    return launch_xfwd_shape<T, Tin, 32, FACES>(f, S, partial, a, batch, fa, s);
+    if (a.nx == 384) return launch_xfwd_shape<T, Tin, Ts, 6, FACES>(f, S, partial, a, batch, fa, s);
+    if (a.nx <= 512) return launch_xfwd_shape<T, Tin, Ts, 8, FACES>(f, S, partial, a, batch, fa, s);
+    if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, Ts, 16, FACES>(f, S, partial, a, batch, fa, s);
+    return launch_xfwd_shape<T, Tin, Ts, 32, FACES>(f, S, partial, a, batch, fa, s);
 }
 
-template <typename T, typename Tin>
-hipError_t launch_xfwd(const Tin* f, cplx<T>* S, double* partial, const XArgs<T>& a, int batch,
+template <typename T, typename Tin, typename Ts>
+hipError_t launch_xfwd(const Tin* f, cplx<Ts>* S, double* partial, const XArgs<T>& a, int batch,
                        const FaceArgs<Tin>* faces, hipStream_t s) {
-    if (faces) return launch_xfwd_any<T, Tin, true>(f, S, partial, a, batch, *faces, s);
+    if (faces) return launch_xfwd_any<T, Tin, Ts, true>(f, S, partial, a, batch, *faces, s);
     const FaceArgs<Tin> none{};
-    return launch_xfwd_any<T, Tin, false>(f, S, partial, a, batch, none, s);
+    return launch_xfwd_any<T, Tin, Ts, false>(f, S, partial, a, batch, none, s);
 }
 
-template <typename T, typename Tout, int MODE, int RMAX>
-static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
-                                    const double* scalars, int gauge_region, double* partial, hipStream_t s) {
+template <typename T, typename Tout, typename Tp, int MODE, int RMAX>
+static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const Tp* uprev, const XArgs<T>& a, int batch,
+                                    const double* shift, const double* scalars, int gauge_region, double* partial,
+                                    hipStream_t s) {
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
     if constexpr (RMAX <= 16) {
         if (x_full<RMAX>(a)) {
-            allow_lds<k_xinv<T, Tout, kXThreads, MODE, RMAX, true>>();
-            hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, MODE, RMAX, true>), dim3(x_launch_grid(nb, sizeof(T) == 4)), dim3(kXThreads),
-                               x_lds_bytes(a), s, S, u, a, shift, scalars, gauge_region, partial, nb);
+            allow_lds<k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, true>>();
+            hipLaunchKernelGGL((k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, true>),
+                               dim3(x_launch_grid(nb, sizeof(T) == 4)), dim3(kXThreads), x_lds_bytes(a), s, S, u,
+                               uprev, a, shift, scalars, gauge_region, partial, nb);
             return hipGetLastError();
         }
     }
     {
-        allow_lds<k_xinv<T, Tout, kXThreads, MODE, RMAX, false>>();
-        hipLaunchKernelGGL((k_xinv<T, Tout, kXThreads, MODE, RMAX, false>), dim3(x_launch_grid(nb, sizeof(T) == 4)), dim3(kXThreads),
-                           x_lds_bytes(a), s, S, u, a, shift, scalars, gauge_region, partial, nb);
+        allow_lds<k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, false>>();
+        hipLaunchKernelGGL((k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, false>),
+                           dim3(x_launch_grid(nb, sizeof(T) == 4)), dim3(kXThreads), x_lds_bytes(a), s, S, u, uprev,
+                           a, shift, scalars, gauge_region, partial, nb);
     }
     return hipGetLastError();
 }
 
-template <typename T, typename Tout, int MODE>
-static hipError_t launch_xinv_any(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift,
-                                  const double* scalars, int gauge_region, double* partial, hipStream_t s) {
+template <typename T, typename Tout, typename Tp, int MODE>
+static hipError_t launch_xinv_any(const cplx<T>* S, Tout* u, const Tp* uprev, const XArgs<T>& a, int batch,
+                                  const double* shift, const double* scalars, int gauge_region, double* partial,
+                                  hipStream_t s) {
     if (a.nx == 384)   // 64 x 6: exact-count form with six values per lane
-        return launch_xinv_shape<T, Tout, MODE, 6>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
+        return launch_xinv_shape<T, Tout, Tp, MODE, 6>(S, u, uprev, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx <= 512)
-        return launch_xinv_shape<T, Tout, MODE, 8>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
+        return launch_xinv_shape<T, Tout, Tp, MODE, 8>(S, u, uprev, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx <= 1024)
-        return launch_xinv_shape<T, Tout, MODE, 16>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
-    return launch_xinv_shape<T, Tout, MODE, 32>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
+        return launch_xinv_shape<T, Tout, Tp, MODE, 16>(S, u, uprev, a, batch, shift, scalars, gauge_region, partial,
+                                                        s);
+    return launch_xinv_shape<T, Tout, Tp, MODE, 32>(S, u, uprev, a, batch, shift, scalars, gauge_region, partial, s);
 }
 
 template <typename T, typename Tout>
 hipError_t launch_xinv(const cplx<T>* S, Tout* u, const XArgs<T>& a, int batch, const double* shift, hipStream_t s) {
-    return launch_xinv_any<T, Tout, XINV_STORE>(S, u, a, batch, shift, (const double*)nullptr, 0, (double*)nullptr,
-                                                s);
+    return launch_xinv_any<T, Tout, Tout, XINV_STORE>(S, u, (const Tout*)nullptr, a, batch, shift,
+                                                      (const double*)nullptr, 0, (double*)nullptr, s);
 }
 
-hipError_t launch_xinv_update(const cplx<float>* S, double* u, const XArgs<float>& a, int batch,
-                              const double* scalars, int gauge_region, double* partial, int accumulate,
-                              hipStream_t s) {
+hipError_t launch_xinv_first(const cplx<float>* S, float* u0, const XArgs<float>& a, int batch, const double* scalars,
+                             int gauge_region, double* partial, hipStream_t s) {
+    // no mean shift: u0 holds the transform's own float values, so storing it
+    // rounds nothing; the gauge shift of the first update removes the mean
+    return launch_xinv_any<float, float, float, XINV_FIRST>(S, u0, (const float*)nullptr, a, batch,
+                                                            (const double*)nullptr, scalars, gauge_region, partial, s);
+}
+
+hipError_t launch_xinv_update(const cplx<float>* S, double* u, const float* uprev, const XArgs<float>& a, int batch,
+                              const double* scalars, int gauge_region, double* partial, int mode, hipStream_t s) {
     const double* shift = scalars + SC_COUNT + batch;   // cmean of the correction solve
-    if (accumulate)
-        return launch_xinv_any<float, double, XINV_UPDATE>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
-    return launch_xinv_any<float, double, XINV_FIRST>(S, u, a, batch, shift, scalars, gauge_region, partial, s);
+    if (mode == XINV_FIRST)
+        return launch_xinv_any<float, double, double, XINV_FIRST>(S, u, (const double*)nullptr, a, batch, shift,
+                                                                  scalars, gauge_region, partial, s);
+    if (uprev)
+        return launch_xinv_any<float, double, float, XINV_UPDATE>(S, u, uprev, a, batch, shift, scalars,
+                                                                  gauge_region, partial, s);
+    return launch_xinv_any<float, double, double, XINV_UPDATE>(S, u, (const double*)nullptr, a, batch, shift, scalars,
+                                                               gauge_region, partial, s);
 }
 
-template hipError_t launch_xfwd<double, double>(const double*, cplx<double>*, double*, const XArgs<double>&, int,
-                                                const FaceArgs<double>*, hipStream_t);
-template hipError_t launch_xfwd<float, float>(const float*, cplx<float>*, double*, const XArgs<float>&, int,
-                                              const FaceArgs<float>*, hipStream_t);
-template hipError_t launch_xfwd<float, double>(const double*, cplx<float>*, double*, const XArgs<float>&, int,
-                                               const FaceArgs<double>*, hipStream_t);
+template hipError_t launch_xfwd<double, double, double>(const double*, cplx<double>*, double*, const XArgs<double>&,
+                                                        int, const FaceArgs<double>*, hipStream_t);
+template hipError_t launch_xfwd<float, float, float>(const float*, cplx<float>*, double*, const XArgs<float>&, int,
+                                                     const FaceArgs<float>*, hipStream_t);
+// refined solve: double arithmetic, float spectra (and the double slots)
+template hipError_t launch_xfwd<double, double, float>(const double*, cplx<float>*, double*, const XArgs<double>&,
+                                                       int, const FaceArgs<double>*, hipStream_t);
+template hipError_t launch_xfwd<double, float, float>(const float*, cplx<float>*, double*, const XArgs<double>&, int,
+                                                      const FaceArgs<float>*, hipStream_t);
 template hipError_t launch_xinv<double, double>(const cplx<double>*, double*, const XArgs<double>&, int,
                                                 const double*, hipStream_t);
 template hipError_t launch_xinv<float, float>(const cplx<float>*, float*, const XArgs<float>&, int, const double*,
                                               hipStream_t);
-template hipError_t launch_xinv<float, double>(const cplx<float>*, double*, const XArgs<float>&, int,
-                                               const double*, hipStream_t);
 
 }  // namespace pp

@@ -337,17 +337,40 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 // chunk's stores, or one chunk's prefetch).  FULL (ny == NYMAX, nz a multiple
 // of NW) removes every data-dependent branch around memory instructions, so the
 // compiler can count them exactly; barriers order LDS only.
-template <typename T, int NYMAX, int NW, bool FULL, bool PERZ>
-__global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
+//
+// The march itself is zpipe_body, which works in precision T on a column it
+// reads (upward) from `icol` in precision Tin and writes (eliminated right-hand
+// sides, and everything on the way down) to `ocol` in precision Tout; the
+// plain solves run it in place (icol == ocol, one precision).  The refined
+// solve's mixed march (k_zpipe_mixed) runs the slots of the smallest x
+// wavenumbers in double from a double copy of their spectra and the others in
+// float, both storing float.
+
+// LDS of one march workgroup in compute precision T.
+template <typename T, int NYMAX, int NW> struct ZpipeLds {
+    static constexpr int LDY = NYMAX + NYMAX / 8;   // work-buffer plane stride (>= padded_len(NYMAX))
+    cplx<T> work[NW * LDY];
+    cplx<T> twl[NYMAX];
+    cplx<T> mkl[NYMAX];
+};
+
+// Precisions: Tin of the column read upward, T of the z recurrences (and their
+// tables, a), Tf of the y transforms (LDS lines, tables af), Tout of everything
+// stored.  YFWD false: icol already holds the y-transformed values (k_ypre),
+// so the way up only eliminates (each thread prefetches its own entries).
+template <typename Tin, typename T, typename Tf, typename Tout, int NYMAX, int NW, bool FULL, bool PERZ, bool YFWD>
+__device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cplx<Tout>* ocol, size_t zs,
+                                           const MidArgs<T>& a, const MidArgs<Tf>& af,
+                                           ZpipeLds<Tf, NYMAX, NW>& L) {
     constexpr int NTH = 64 * NW;
     constexpr int kSZ = NW;                      // planes per chunk = wavefronts per workgroup
     constexpr int EPL = NYMAX / 64;              // plane elements per lane
     constexpr int OWN = NYMAX / NTH;             // z-recurrence entries per thread
-    constexpr int LDY = NYMAX + NYMAX / 8;       // work-buffer plane stride (>= padded_len(NYMAX))
+    constexpr int LDY = ZpipeLds<Tf, NYMAX, NW>::LDY;
     static_assert(EPL == kSZ * OWN, "one prefetch buffer serves both directions");
-    __shared__ __align__(16) cplx<T> work[kSZ * LDY];
-    __shared__ __align__(16) cplx<T> twl[NYMAX];
-    __shared__ __align__(16) cplx<T> mkl[NYMAX];
+    cplx<Tf>* work = L.work;
+    cplx<Tf>* twl = L.twl;
+    cplx<Tf>* mkl = L.mkl;
     const int m = blockIdx.x, b = blockIdx.y;
     const int ny = FULL ? NYMAX : a.ny;
     const int nz = a.nz;
@@ -355,22 +378,20 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int i = tid; i < ny; i += NTH) {
-        twl[i] = a.twy[i];
-        mkl[i] = a.mky[i];
+        twl[i] = af.twy[i];
+        mkl[i] = af.mky[i];
     }
     // periodic y on lines of 512: the transforms take their first (forward) or
     // last (inverse) stage in registers (w512_*)
     constexpr bool R512 = FULL && NYMAX == 512;
     const bool reg512 = R512 && a.by == BC_P;
-    using Tw512 = std::conditional_t<sizeof(T) == 4, Tw512Reg<T>, Tw512Lds<T>>;
+    using Tw512 = std::conditional_t<sizeof(Tf) == 4, Tw512Reg<Tf>, Tw512Lds<Tf>>;
     Tw512 w512;
-    if constexpr (sizeof(T) == 4) {
-        if constexpr (R512) w512 = tw512_regs<T>(a.twy, lane);
+    if constexpr (sizeof(Tf) == 4) {
+        if constexpr (R512) w512 = tw512_regs<Tf>(af.twy, lane);
     } else {
-        w512 = Tw512Lds<T>{twl, lane};
+        w512 = Tw512Lds<Tf>{twl, lane};
     }
-    cplx<T>* col = S + (size_t)b * a.slots * nz * ny + (size_t)m * a.sstride;
-    const size_t zs = (size_t)a.zstride;
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
     const bool sing = a.singular && (m == 0);
@@ -446,14 +467,24 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
         const bool lastrow = (z == nz - 1), tab = (z < elen[o]);
         return mk<T>(lastrow ? wl.x : (tab ? p.x : wi.x), lastrow ? wl.y : (tab ? p.y : wi.y));
     };
-    // upward prefetch: elements y = lane + 64 k of plane zc + wave (clamped to the last plane)
+    // upward prefetch (clamped to the last plane): YFWD, elements y = lane + 64 k
+    // of plane zc + wave; otherwise the thread's own entries of planes zc .. zc+NW-1
     cplx<T> pre[EPL];
     auto load_plane = [&](int zc) __attribute__((always_inline)) {
-        const cplx<T>* src = col + (size_t)min(zc + wave, nz - 1) * zs;
+        if constexpr (YFWD) {
+            const cplx<Tin>* src = icol + (size_t)min(zc + wave, nz - 1) * izs;
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) {
-            const int y = lane + 64 * k;
-            pre[k] = src[(FULL || y < ny) ? y : 0];
+            for (int k = 0; k < EPL; ++k) {
+                const int y = lane + 64 * k;
+                pre[k] = cvt<T>(src[(FULL || y < ny) ? y : 0]);
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < kSZ; ++l) {
+#pragma unroll
+                for (int o = 0; o < OWN; ++o)
+                    pre[l * OWN + o] = cvt<T>(icol[(size_t)min(zc + l, nz - 1) * izs + ec[o]]);
+            }
         }
     };
     // downward prefetch: the thread's entries of planes zc .. zc+NW-1 (clamped to the last plane)
@@ -461,7 +492,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
 #pragma unroll
         for (int l = 0; l < kSZ; ++l) {
 #pragma unroll
-            for (int o = 0; o < OWN; ++o) pre[l * OWN + o] = col[(size_t)min(zc + l, nz - 1) * zs + ec[o]];
+            for (int o = 0; o < OWN; ++o) pre[l * OWN + o] = cvt<T>(ocol[(size_t)min(zc + l, nz - 1) * zs + ec[o]]);
         }
     };
 
@@ -474,24 +505,31 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     auto up_chunk = [&](int c) __attribute__((always_inline)) {
         const int zc = c * kSZ;
         const int nl = FULL ? kSZ : min(kSZ, nz - zc);
+        // !YFWD: this chunk's right-hand sides, taken out of the prefetch buffer
+        cplx<T> cur[YFWD ? 1 : EPL];
+        if constexpr (!YFWD) {
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) cur[k] = pre[k];
+            load_plane(min(zc + kSZ, last));
+        } else {
         lds_barrier();   // the previous recurrences are done with the work buffer
-        cplx<T>* line = work + wave * LDY;
+        cplx<Tf>* line = work + wave * LDY;
         const bool own = FULL || wave < nl;
-        cplx<T> v[EPL];
+        cplx<Tf> v[EPL];
         if (reg512) {
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) v[k] = pre[k];
+            for (int k = 0; k < EPL; ++k) v[k] = cvt<Tf>(pre[k]);
         } else if (own) {
             // prefetched plane -> work plane, reordered for the forward transform
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 const int y = lane + 64 * k;
                 if (FULL || y < ny) {
-                    cplx<T> x = pre[k];
+                    cplx<Tf> x = cvt<Tf>(pre[k]);
                     int pos = y;
                     if (a.by != BC_P) {
                         pos = makhoul_pos(y, ny);
-                        if (a.by == BC_D && (y & 1)) x = mk<T>(-x.x, -x.y);
+                        if (a.by == BC_D && (y & 1)) x = mk<Tf>(-x.x, -x.y);
                     }
                     line[pad(pos)] = x;
                 }
@@ -500,9 +538,9 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
         load_plane(min(zc + kSZ, last));
         if (reg512) {
             if constexpr (R512) {
-                w512_first<false, T>(v, line, lane);
-                w512_second<false, T>(line, w512, lane);
-                w512_last<false, T>(line, w512, lane, v);
+                w512_first<false, Tf>(v, line, lane);
+                w512_second<false, Tf>(line, w512, lane);
+                w512_last<false, Tf>(line, w512, lane, v);
             }
             // each lane writes back the elements it read
 #pragma unroll
@@ -511,38 +549,39 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
                 wave_lds_sync();
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0 || 2 * k >= ny) continue;
-                    const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
-                    line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
-                    line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+                    const cplx<Tf> zk = line[pad(k)], zr = line[pad(ny - k)];
+                    line[pad(k)] = mk<Tf>(Tf(0.5) * (zk.x + zr.x), Tf(0.5) * (zk.y - zr.y));
+                    line[pad(ny - k)] = mk<Tf>(Tf(0.5) * (zk.y + zr.y), Tf(0.5) * (zr.x - zk.x));
                 }
             }
         } else if (own) {
             wave_lds_sync();
-            wfft<EPL, false, T>(line, a.fy, twl, lane);
+            wfft<EPL, false, Tf>(line, af.fy, twl, lane);
             if (a.by != BC_P) {
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0) continue;
-                    const cplx<T> vk = line[pad(k)];
-                    const cplx<T> wk = mkl[k];
+                    const cplx<Tf> vk = line[pad(k)];
+                    const cplx<Tf> wk = mkl[k];
                     if (2 * k == ny) {
-                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vk, wk)), T(0.5));
+                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vk, wk)), Tf(0.5));
                     } else {
-                        const cplx<T> vr = line[pad(ny - k)];
-                        const cplx<T> wr = mkl[ny - k];
-                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), T(0.5));
-                        line[pad(ny - k)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), T(0.5));
+                        const cplx<Tf> vr = line[pad(ny - k)];
+                        const cplx<Tf> wr = mkl[ny - k];
+                        line[pad(k)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), Tf(0.5));
+                        line[pad(ny - k)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), Tf(0.5));
                     }
                 }
             } else if (sep) {
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0 || 2 * k >= ny) continue;
-                    const cplx<T> zk = line[pad(k)], zr = line[pad(ny - k)];
-                    line[pad(k)] = mk<T>(T(0.5) * (zk.x + zr.x), T(0.5) * (zk.y - zr.y));
-                    line[pad(ny - k)] = mk<T>(T(0.5) * (zk.y + zr.y), T(0.5) * (zr.x - zk.x));
+                    const cplx<Tf> zk = line[pad(k)], zr = line[pad(ny - k)];
+                    line[pad(k)] = mk<Tf>(Tf(0.5) * (zk.x + zr.x), Tf(0.5) * (zk.y - zr.y));
+                    line[pad(ny - k)] = mk<Tf>(Tf(0.5) * (zk.y + zr.y), Tf(0.5) * (zr.x - zk.x));
                 }
             }
         }
         lds_barrier();
+        }
         // forward elimination over the chunk; eliminated right-hand sides go to HBM
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
@@ -562,7 +601,9 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
                 if (FULL || l < nl) {
                     const int z = zc + l;
                     const cplx<T> w = pivot(z, l, o);
-                    cplx<T> d = cscale(work[l * LDY + pad(e)], scale);
+                    cplx<T> d;
+                    if constexpr (YFWD) d = cscale(cvt<T>(work[l * LDY + pad(e)]), scale);
+                    else d = cscale(cur[l * OWN + o], scale);
                     if (sing && e == 0) d.x -= proj;
                     if constexpr (PERZ) {
                         if (zc < alw[o]) {
@@ -571,7 +612,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
                         }
                     }
                     prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
-                    col[(size_t)z * zs + e] = prev;
+                    ocol[(size_t)z * zs + e] = cvt<Tout>(prev);
                 }
             }
             st[o] = prev;
@@ -632,7 +673,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
                         }
                         un = mk<T>(nxt.x - corr[o].x * qnext[o].x, nxt.y - corr[o].y * qnext[o].y);
                     }
-                    work[l * LDY + pad(e)] = un;
+                    work[l * LDY + pad(e)] = cvt<Tf>(un);
                     if (sing && e == 0) csum += (double)un.x;
                 }
             }
@@ -644,49 +685,49 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
         load_piv(zn);
         // inverse y transform of this wave's plane, written straight to HBM
         if (FULL || wave < nl) {
-            cplx<T>* line = work + wave * LDY;
+            cplx<Tf>* line = work + wave * LDY;
             if (a.by != BC_P) {
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0) continue;
-                    const cplx<T> xk = line[pad(k)];
+                    const cplx<Tf> xk = line[pad(k)];
                     if (2 * k == ny) {
-                        line[pad(k)] = cmulc(mk<T>(xk.x + xk.y, xk.y - xk.x), mkl[k]);
+                        line[pad(k)] = cmulc(mk<Tf>(xk.x + xk.y, xk.y - xk.x), mkl[k]);
                     } else {
-                        const cplx<T> xr = line[pad(ny - k)];
-                        line[pad(k)] = cmulc(mk<T>(xk.x + xr.y, xk.y - xr.x), mkl[k]);
-                        line[pad(ny - k)] = cmulc(mk<T>(xr.x + xk.y, xr.y - xk.x), mkl[ny - k]);
+                        const cplx<Tf> xr = line[pad(ny - k)];
+                        line[pad(k)] = cmulc(mk<Tf>(xk.x + xr.y, xk.y - xr.x), mkl[k]);
+                        line[pad(ny - k)] = cmulc(mk<Tf>(xr.x + xk.y, xr.y - xk.x), mkl[ny - k]);
                     }
                 }
             } else if (sep) {
                 for (int k = lane; k < half; k += 64) {
                     if (k == 0 || 2 * k >= ny) continue;
-                    const cplx<T> A = line[pad(k)], B = line[pad(ny - k)];
-                    line[pad(k)] = mk<T>(A.x - B.y, A.y + B.x);
-                    line[pad(ny - k)] = mk<T>(A.x + B.y, B.x - A.y);
+                    const cplx<Tf> A = line[pad(k)], B = line[pad(ny - k)];
+                    line[pad(k)] = mk<Tf>(A.x - B.y, A.y + B.x);
+                    line[pad(ny - k)] = mk<Tf>(A.x + B.y, B.x - A.y);
                 }
             }
             wave_lds_sync();
-            cplx<T>* dst = col + (size_t)(zc + wave) * zs;
+            cplx<Tout>* dst = ocol + (size_t)(zc + wave) * zs;
             if (reg512) {
-                cplx<T> v[EPL];
+                cplx<Tf> v[EPL];
                 if constexpr (R512) {
-                    w512_first_lds<true, T>(line, lane);
-                    w512_second<true, T>(line, w512, lane);
-                    w512_last<true, T>(line, w512, lane, v);
+                    w512_first_lds<true, Tf>(line, lane);
+                    w512_second<true, Tf>(line, w512, lane);
+                    w512_last<true, Tf>(line, w512, lane, v);
                 }
 #pragma unroll
-                for (int t = 0; t < EPL; ++t) dst[lane + 64 * t] = v[t];
+                for (int t = 0; t < EPL; ++t) dst[lane + 64 * t] = cvt<Tout>(v[t]);
             } else {
-                wfft<EPL, true, T>(line, a.fy, twl, lane);
+                wfft<EPL, true, Tf>(line, af.fy, twl, lane);
 #pragma unroll
                 for (int k = 0; k < EPL; ++k) {
                     const int y = lane + 64 * k;
                     if (FULL || y < ny) {
                         int pos = y;
                         if (a.by != BC_P) pos = makhoul_pos(y, ny);
-                        cplx<T> x = line[pad(pos)];
-                        if (a.by == BC_D && (y & 1)) x = mk<T>(-x.x, -x.y);
-                        dst[y] = x;
+                        cplx<Tf> x = line[pad(pos)];
+                        if (a.by == BC_D && (y & 1)) x = mk<Tf>(-x.x, -x.y);
+                        dst[y] = cvt<Tout>(x);
                     }
                 }
             }
@@ -695,6 +736,103 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
     down_chunk(nchunks - 1);
     for (int c = nchunks - 2; c >= 0; --c) down_chunk(c);
     if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
+}
+
+// The march in one precision, in place.
+template <typename T, int NYMAX, int NW, bool FULL, bool PERZ>
+__global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
+    __shared__ __align__(16) ZpipeLds<T, NYMAX, NW> L;
+    cplx<T>* col = S + (size_t)blockIdx.y * a.slots * a.nz * a.ny + (size_t)blockIdx.x * a.sstride;
+    zpipe_body<T, T, T, T, NYMAX, NW, FULL, PERZ, true>(col, (size_t)a.zstride, col, (size_t)a.zstride, a, a, L);
+}
+
+// The refined solve's march: slots lo0 .. lo0+nlo-1 (the smallest x
+// wavenumbers, whose z systems are the least well conditioned) take their
+// right-hand sides from Slo[b][z][k][y], already transformed along y in double
+// (k_ypre), and run the recurrences in double; everything else is float, and
+// every result goes to S in float.  One workgroup per slot as in k_zpipe; the
+// branch is uniform over the workgroup.  (Doing the double slots' y transforms
+// here instead made those workgroups the last to finish: 0.69 against 0.52 ms
+// at 512^3.)
+template <int NYMAX, int NW, bool FULL, bool PERZ>
+__global__ __launch_bounds__(64 * NW) void k_zpipe_mixed(const cplx<double>* __restrict__ Slo,
+                                                         cplx<float>* __restrict__ S, MidArgs<double> ad,
+                                                         MidArgs<float> af, int lo0, int nlo) {
+    __shared__ __align__(16) ZpipeLds<float, NYMAX, NW> L;
+    const int k = (int)blockIdx.x - lo0;
+    cplx<float>* col = S + (size_t)blockIdx.y * af.slots * af.nz * af.ny + (size_t)blockIdx.x * af.sstride;
+    if (k >= 0 && k < nlo) {
+        const cplx<double>* icol = Slo + ((size_t)blockIdx.y * af.nz * nlo + k) * af.ny;
+        zpipe_body<double, double, float, float, NYMAX, NW, FULL, PERZ, false>(icol, (size_t)nlo * af.ny, col,
+                                                                               (size_t)af.zstride, ad, af, L);
+    } else {
+        zpipe_body<float, float, float, float, NYMAX, NW, FULL, PERZ, true>(col, (size_t)af.zstride, col,
+                                                                            (size_t)af.zstride, af, af, L);
+    }
+}
+
+// Forward y transform, in double and in place, of the double slots of the
+// refined solve (Slo[b][z][k][y], k < nlo, slot lo0 + k): one wavefront per
+// plane, four planes per workgroup; the same pre- and post-processing as the
+// march's upward transform.
+constexpr int kYpreWaves = 4;
+template <int EPL>
+__global__ __launch_bounds__(64 * kYpreWaves) void k_ypre(cplx<double>* __restrict__ Slo, MidArgs<double> a,
+                                                           int lo0, int nlo, int nplanes) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ny = a.ny, ldy = a.ldy;
+    cplx<double>* twl = reinterpret_cast<cplx<double>*>(smem);
+    cplx<double>* mkl = twl + ny;
+    cplx<double>* line = mkl + ny + (threadIdx.x >> 6) * ldy;
+    for (int i = threadIdx.x; i < ny; i += 64 * kYpreWaves) {
+        twl[i] = a.twy[i];
+        mkl[i] = a.mky[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int pl = blockIdx.x * kYpreWaves + (threadIdx.x >> 6);   // plane index (b, z, k)
+    if (pl >= nplanes) return;
+    const int k = pl % nlo;
+    const int m = lo0 + k;
+    const bool pairslot = (a.bx != BC_P) || (m == 0);
+    const bool sep = (a.by == BC_P) && pairslot;
+    const int half = (ny >> 1) + 1;
+    cplx<double>* src = Slo + (size_t)pl * ny;
+    for (int y = lane; y < ny; y += 64) {
+        cplx<double> x = src[y];
+        int pos = y;
+        if (a.by != BC_P) {
+            pos = makhoul_pos(y, ny);
+            if (a.by == BC_D && (y & 1)) x = mk<double>(-x.x, -x.y);
+        }
+        line[pad(pos)] = x;
+    }
+    wave_lds_sync();
+    wfft<EPL, false, double>(line, a.fy, twl, lane);
+    if (a.by != BC_P) {
+        for (int q = lane; q < half; q += 64) {
+            if (q == 0) continue;
+            const cplx<double> vk = line[pad(q)];
+            const cplx<double> wk = mkl[q];
+            if (2 * q == ny) {
+                line[pad(q)] = cscale(cadd(cmul(wk, vk), cmulc(vk, wk)), 0.5);
+            } else {
+                const cplx<double> vr = line[pad(ny - q)];
+                const cplx<double> wr = mkl[ny - q];
+                line[pad(q)] = cscale(cadd(cmul(wk, vk), cmulc(vr, wk)), 0.5);
+                line[pad(ny - q)] = cscale(cadd(cmul(wr, vr), cmulc(vk, wr)), 0.5);
+            }
+        }
+    } else if (sep) {
+        for (int q = lane; q < half; q += 64) {
+            if (q == 0 || 2 * q >= ny) continue;
+            const cplx<double> zk = line[pad(q)], zr = line[pad(ny - q)];
+            line[pad(q)] = mk<double>(0.5 * (zk.x + zr.x), 0.5 * (zk.y - zr.y));
+            line[pad(ny - q)] = mk<double>(0.5 * (zk.y + zr.y), 0.5 * (zr.x - zk.x));
+        }
+    }
+    wave_lds_sync();
+    for (int y = lane; y < ny; y += 64) src[y] = line[pad(y)];
 }
 
 template <typename T, int NYMAX, int NW, bool FULL>
@@ -741,6 +879,39 @@ hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s)
         else return launch_pipe_any<T, 1024, 4>(S, a, batch, s);
     }
     return launch_mid_shape<T, 32, 4>(S, a, batch, s);
+}
+
+template <int NYMAX, int NW, bool FULL>
+static hipError_t launch_mixed(const cplx<double>* Slo, cplx<float>* S, const MidArgs<double>& ad,
+                               const MidArgs<float>& af, int lo0, int nlo, int batch, hipStream_t s) {
+    const dim3 grid(af.slots, batch), block(64 * NW);
+    if (af.zper)
+        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, true>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
+    else
+        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, false>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
+    return hipGetLastError();
+}
+
+bool mixed_march_supported(int ny, int zsolver) { return zsolver == 0 && ny <= 512; }
+
+hipError_t launch_mid_mixed(const cplx<double>* Slo, cplx<float>* S, const MidArgs<double>& ad,
+                            const MidArgs<float>& af, int lo0, int nlo, int batch, hipStream_t s) {
+    if (nlo > 0) {
+        const int nplanes = nlo * af.nz * batch;
+        const size_t lds = (2 * (size_t)af.ny + (size_t)kYpreWaves * af.ldy) * sizeof(cplx<double>);
+        cplx<double>* lo = const_cast<cplx<double>*>(Slo);
+        const int grid = (nplanes + kYpreWaves - 1) / kYpreWaves;
+        if (af.ny <= 384) hipLaunchKernelGGL(k_ypre<6>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
+        else hipLaunchKernelGGL(k_ypre<8>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (af.ny == 384) {
+        if (af.nz % 6 == 0) return launch_mixed<384, 6, true>(Slo, S, ad, af, lo0, nlo, batch, s);
+        return launch_mixed<384, 6, false>(Slo, S, ad, af, lo0, nlo, batch, s);
+    }
+    if (af.ny == 512 && af.nz % 8 == 0) return launch_mixed<512, 8, true>(Slo, S, ad, af, lo0, nlo, batch, s);
+    return launch_mixed<512, 8, false>(Slo, S, ad, af, lo0, nlo, batch, s);
 }
 
 template hipError_t launch_mid<double>(cplx<double>*, const MidArgs<double>&, int, hipStream_t);
