@@ -39,9 +39,11 @@ typedef struct pp_plan_s* pp_plan;
 /* Arithmetic of a plan.
  *   PP_F64          f, u are double; transforms and z-solves in double.
  *   PP_F32          f, u are float; transforms and z-solves in float.
- *   PP_F32_REFINED  f, u are double; every solve runs in float, wrapped in
- *                   iterative refinement whose residual (the 7-point stencil of
- *                   Eq. 3 with the face ghost rules) and solution update are
+ *   PP_F32_REFINED  f, u are double; every solve runs in float (save the x
+ *                   transform's arithmetic and the lowest x-wavenumber slots,
+ *                   see pp_plan_set_refinement), wrapped in iterative
+ *                   refinement whose residual (the 7-point stencil of Eq. 3
+ *                   with the face ghost rules) and solution update are
  *                   accumulated in double on the GPU. */
 typedef enum { PP_F64 = 0, PP_F32 = 1, PP_F32_REFINED = 2 } pp_dtype;
 
@@ -82,8 +84,8 @@ typedef enum {
  *   periodic z  nz >= 3;
  *   PCR / CR-P  z not periodic (PP_ERR_BC), nz and ny at most 512 (set_zsolver).
  * Device workspace: pp_plan_workspace_bytes(p); about 8 B (PP_F64, and
- * PP_F32_REFINED) or 4 B (PP_F32) per grid point and batch entry, plus the
- * plan tables. */
+ * PP_F32_REFINED; 16 B with rows over 512) or 4 B (PP_F32) per grid point and
+ * batch entry, plus the plan tables. */
 
 /* Create a plan (host only; no GPU call).
  *   nx, ny, nz  cells per direction, >= 1.  nx and ny must factor as 2^a 3^b.
@@ -120,10 +122,15 @@ typedef enum { PP_ZSOLVER_THOMAS = 0, PP_ZSOLVER_PCR = 1, PP_ZSOLVER_CR = 2 } pp
 pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
 
 /* Refinement controls for PP_F32_REFINED: stop once the estimated relative
- * error of u (max-norm; the size of the next correction predicted from the
- * last two corrections, or the first correction itself while there is only
- * one) is at most tol, or after max_iter correction steps (max_iter = 0 runs
- * the float solve alone and reports PP_ERR_NOT_CONVERGED). */
+ * error of u (max-norm) is at most tol, or after max_iter correction steps
+ * (max_iter = 0 runs the float solve alone and reports PP_ERR_NOT_CONVERGED).
+ * The estimate is the size of the next correction: the last correction times
+ * the ratio of the last two corrections, or, after the first, times the first
+ * correction itself (the float solve's relative error, which the correction's
+ * solve is taken to repeat).  The float solves transform along x in double and
+ * keep the spectra of the 16 lowest x-wavenumber slots in double (rows and y
+ * lines up to 512 in the z march; otherwise those slots run in float too and
+ * more corrections may be needed). */
 pp_status pp_plan_set_refinement(pp_plan p, double tol, int max_iter);
 
 /* Bytes of device workspace the caller must pass to pp_solve/pp_solve_adjoint

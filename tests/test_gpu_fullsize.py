@@ -96,6 +96,7 @@ def test_div_ppn_512_backward_error_and_refined():
     d = float((ur - u).abs().max() / u.abs().max())
     banner(f"refined corrections {its}, diff vs f64 {d:.2e}")
     assert d < 1e-12
+    assert its == 1   # one correction reaches the tolerance at this shape
     u32, _ = _plan_solve(wl, dtype="f32", f=wl["f"].astype(np.float32))
     assert float((u32.double() - u).abs().max() / u.abs().max()) < 1e-5
     del u, ur, u32

@@ -108,6 +108,44 @@ def test_refined_matches_oracle(bc):
         assert rel_max(u, uo) < 1e-12, (its, rel)
 
 
+# One correction reaches the 1e-12 bar: the refinement run with exactly one
+# correction (tolerance 0, so the plan reports PP_ERR_NOT_CONVERGED) matches
+# the oracle; shapes where one direction is much finer than the others (the
+# residual's float rounding limited the first correction there), the
+# exact-count forms (fused residual for rows of 384 / 512, stored double
+# residual for rows of 1024), general forms, faces, batches, both gauges.
+ONE_CORRECTION = [((8, 8, 512), "PPPPNN", False), ((8, 16, 1024), "PPPPNN", True), ((16, 512, 16), "PPPPNN", True),
+                  ((16, 512, 512), "PPPPNN", True), ((8, 8, 512), "DDNNDN", True), ((12, 384, 384), "DDDDDD", False),
+                  ((9, 24, 36), "NNPPNN", True), ((7, 12, 1024), "DDNNNN", False), ((24, 48, 18), "PPPPPP", False)]
+
+
+@pytest.mark.parametrize("case", ONE_CORRECTION, ids=lambda c: f"{c[1]}-{c[0]}-{'faces' if c[2] else 'nofaces'}")
+@pytest.mark.parametrize("gauge", ["mean", "pin"])
+def test_refined_one_correction(case, gauge):
+    import torch
+    from paper_1909_05423_amd import Plan, _lib
+    from gpu_util import banner, rel_max, to_dev
+    shape, bc, with_faces = case
+    banner(f"one correction {bc} {shape} faces={with_faces} gauge={gauge}")
+    rng = np.random.default_rng(61 + sum(map(ord, bc)) + shape[2])
+    h = tuple(1.0 / n for n in shape[::-1])
+    batch = 2
+    f = rng.standard_normal((batch,) + shape)
+    plan = Plan(shape, bc, h, dtype="f32_refined", batch=batch, gauge=gauge, refine_tol=0.0, refine_max_iter=1)
+    faces = None
+    if with_faces:
+        faces = [None if bc[i] == "P" else rng.standard_normal(plan.face_shape(i)) for i in range(6)]
+    u = torch.empty((batch,) + shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.PPError) as ei:
+        plan.solve(to_dev(f), out=u, faces=None if faces is None else [None if g is None else to_dev(g) for g in faces])
+    assert ei.value.status == -7
+    torch.cuda.synchronize()
+    un = u.cpu().numpy()
+    for b in range(batch):
+        fb = None if faces is None else [None if g is None else g[b] for g in faces]
+        assert rel_max(un[b], oracle.solve(f[b], bc, h, gauge, faces=fb)) < 1e-12, b
+
+
 def test_batched_equals_single():
     from gpu_util import rel_max
     rng = np.random.default_rng(19)
