@@ -240,12 +240,19 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
     // RES: the value of u0 at column n - 1 (dir -1) or n + 1 (dir +1) of the row
     // held in c (exact-count form: lane l holds columns l + 64 r), from the
     // adjacent lane; past the x faces the periodic image or the ghost rule
+    // (DPP wave_ror:1 gives lane l the value of lane l - 1, lane 0 that of lane
+    // 63; wave_rol:1 lane l + 1, lane 63 that of lane 0)
+    auto rot1 = [&](float v, int dir) -> float {
+        const int iv = __float_as_int(v);
+        const int o = dir < 0 ? __builtin_amdgcn_update_dpp(0, iv, 0x13C, 0xF, 0xF, false)
+                              : __builtin_amdgcn_update_dpp(0, iv, 0x134, 0xF, 0xF, false);
+        return __int_as_float(o);
+    };
     auto xnb = [&](const float (&c)[RR], int r, int dir) -> double {
         if constexpr (RES && FULL) {
-            const int src = (lane + dir) & 63;
             const int rw = (r + dir + RMAX) % RMAX;   // the register of the wrapped-around lane
-            const float t1 = __shfl(c[r], src, 64);
-            const float t2 = __shfl(c[rw], src, 64);
+            const float t1 = rot1(c[r], dir);
+            const float t2 = rot1(c[rw], dir);
             const bool wrap = dir < 0 ? (lane == 0) : (lane == 63);
             const int n = lane + 64 * r;
             const bool face = dir < 0 ? (n == 0) : (n == nx - 1);
@@ -571,10 +578,14 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
             partial[3 * rec + 2] = 0.0;
         }
     }
-    double acc = 0.0, dmax = 0.0, umax = 0.0;
+    // dmax, umax by fmax (one instruction; it drops NaN), so a NaN correction is
+    // carried by the sum chk into dmax at the flush.  The first solve (XINV_FIRST)
+    // needs no maxima: its relative correction is 1 by definition.
+    double acc = 0.0, dmax = 0.0, umax = 0.0, chk = 0.0;
     int cur_b = -1;
     auto flush = [&]() {
         if (!UPD) return;
+        if (chk != chk) dmax = chk;
         const double s_ = wave_sum(acc), d_ = wave_max(dmax), u_ = wave_max(umax);
         if (lane == 0 && cur_b >= 0) {
             const size_t rec = cur_b * rec_per_batch + (size_t)blockIdx.x * NW + wave;
@@ -585,6 +596,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
         acc = 0.0;
         dmax = 0.0;
         umax = 0.0;
+        chk = 0.0;
     };
 
     cplx<T> sa[PAIRS], sb[PAIRS];
@@ -723,8 +735,11 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                             const double un = (double)(Tout)(uo[UR > 1 ? 2 * k + part : 0] + d - gshift);
                             st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
-                            dmax = nmax(dmax, fabs(d));
-                            umax = nmax(umax, fabs(un));
+                            if constexpr (MODE == XINV_UPDATE) {
+                                dmax = fmax(dmax, fabs(d));
+                                umax = fmax(umax, fabs(un));
+                                chk += d;
+                            }
                         }
                     }
                 }
@@ -747,8 +762,11 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
                             const double un = (double)(Tout)((MODE == XINV_UPDATE ? (double)prv[idx] : 0.0) + d - gshift);
                             st_stream(dst + idx, (Tout)un);
                             if (gauge_region == 1 || (gauge_region == 2 && xb.z == 0)) acc += un;
-                            dmax = nmax(dmax, fabs(d));
-                            umax = nmax(umax, fabs(un));
+                            if constexpr (MODE == XINV_UPDATE) {
+                                dmax = fmax(dmax, fabs(d));
+                                umax = fmax(umax, fabs(un));
+                                chk += d;
+                            }
                         }
                     }
                 }
