@@ -148,8 +148,9 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
     // periodic rows of 512, double spectra: the transform's first stage runs
     // on the row registers (w512_first; in float the extra registers cost more
     // occupancy than the LDS round trip saves)
-    // (not with the fused residual, whose neighbour values need the registers)
-    constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8 && !RES;
+    // (not with the fused residual, whose neighbour values need the registers,
+    // nor with the split store, which spilled with it)
+    constexpr bool R512 = FULL && RMAX == 8 && sizeof(T) == 8 && !RES && !SPLIT;
     const bool reg512 = R512 && a.bx == BC_P;
 
     // register r: line j = wave + NW * (r / epl), column n = lane + 64 * (r % epl)
@@ -210,6 +211,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
     };
     // RES: u0 of the rows outside the pair in y (below a; above b, or above a
     // when b is past the end) and of the neighbouring planes, for block blk
+    // (issued when the block is formed: issued one block ahead, after the
+    // transform, they cost registers the kernel does not have, 3.00 -> 3.09 ms)
     auto fetch_nb = [&](int blk) {
         if constexpr (RES) {
             const XBlock xb = x_block(blk, nyb, nz, ty);
@@ -489,7 +492,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(kXfwdMinWav
                     return;
                 }
             }
-            put_spec<Ts>(dstS + (size_t)m * a.sstride + (size_t)xb.z * a.zstride + y, cvt<Ts>(v));
+            // (the float spectra of the double-arithmetic kernel are stored
+            // normally: streamed, its launch took 0.47 instead of 0.40 ms at 512^3)
+            if constexpr (SPLIT) dstS[(size_t)m * a.sstride + (size_t)xb.z * a.zstride + y] = cvt<Ts>(v);
+            else put_spec<Ts>(dstS + (size_t)m * a.sstride + (size_t)xb.z * a.zstride + y, cvt<Ts>(v));
         };
         if (FULL) {
 #pragma unroll
