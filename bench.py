@@ -61,6 +61,26 @@ def algorithmic_bytes(plan_shape, batch, slots, elem_in, elem_spec):
     }
 
 
+def refined_bytes(plan_shape, batch, slots, corrections):
+    """Algorithmic bytes of one refined solve with the given number of
+    corrections (rows up to 512: the first correction's residual fused into its
+    x transform), per kernel group: the first solve reads f (8 B/pt), writes
+    float spectra, marches them (read + write up and down) and writes the float
+    first solution u0; the first correction reads f and u0, marches, and reads
+    u0 to write u (8 B/pt); later corrections read and write u itself."""
+    nz, ny, nx = plan_shape
+    n = nx * ny * nz * batch
+    spec = slots * ny * nz * batch * 8             # float spectra
+    xf = (n * 8 + spec) + (n * 8 + n * 4 + spec)
+    zm = 2 * 4 * spec
+    xi = (spec + n * 4) + (spec + n * 4 + n * 8)
+    for _ in range(max(0, corrections - 1)):
+        xf += n * 8 + n * 8 + n * 4 + n * 4 + spec  # residual (f, u in; float r out) + x transform of r
+        zm += 4 * spec
+        xi += spec + 2 * n * 8
+    return {"x_forward": xf, "z_march": zm, "x_inverse": xi}
+
+
 def traffic_for(group, workload, dtype):
     """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
     scaled by the copy-kernel calibration), if taken on the current kernels."""
@@ -121,31 +141,48 @@ def roofline_block(per, abytes, workload, dtype, ny):
                 bytes_per_launch=abytes[best], avg_launch_ms=round(k["avg_ms"], 5))
 
 
-def device_copy_bandwidth(reps=10):
-    """Read + write bandwidth of a plain 1 GiB device-to-device copy (torch copy_),
-    the practical ceiling for a kernel that streams its input once and its
-    output once."""
+def device_copy_bandwidth(lib, reps=10):
+    """Read + write bandwidth of a 1 GiB device-to-device copy: the library's
+    streaming copy (pp_stream_copy: 16-byte non-temporal loads and stores,
+    persistent grid), the practical ceiling for a kernel that streams its
+    input once and its output once; and torch's copy_ beside it."""
+    import ctypes
     import torch
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
     b = torch.empty_like(a)
-    b.copy_(a)
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(reps):
-        b.copy_(a)
-    end.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / reps
-    nbytes = 2 * a.numel() * a.element_size()
+    nbytes = a.numel() * a.element_size()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def own():
+        st = lib.pp_stream_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nbytes, stream)
+        if st != 0:
+            raise RuntimeError(f"pp_stream_copy: {st}")
+
+    out = {}
+    for name, fn in (("stream_copy", own), ("torch_copy", lambda: b.copy_(a))):
+        fn()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(reps):
+            fn()
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / reps
+        out[name] = 2 * nbytes / (ms * 1e-3) / 1e9
+    if not torch.equal(a, b):
+        raise RuntimeError("device copy check failed")
     del a, b
-    return nbytes / (ms * 1e-3) / 1e9
+    return out
 
 
 def cpu_baseline(workload_name, min_seconds=10.0, max_reps=8):
-    """The oracle, timed on this host, on the same recipe at 256^3 (1/8 of the
-    points), repeated until about min_seconds of CPU work have run."""
+    """The oracle, timed on this host, on the same recipe on a 512 x 512 x 32
+    slab of the 512^3 grid, repeated until about min_seconds of CPU work have
+    run.  The oracle's transforms are direct sums over whole 512-long x and y
+    lines, so their cost per point is that of the full grid; the z solves cost
+    the same per point at any nz."""
     import numpy as np
     import oracle
     import workloads
@@ -154,7 +191,8 @@ def cpu_baseline(workload_name, min_seconds=10.0, max_reps=8):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
-    shape = (256, 256, 256)
+    full = workloads.WORKLOADS[workload_name]["shape"]
+    shape = (min(32, full[0]), full[1], full[2])
     wl = workloads.make(workload_name, shape=shape, batch=1)
     reps, dt = 0, 0.0
     while reps < max_reps and (reps == 0 or dt < min_seconds):
@@ -165,8 +203,9 @@ def cpu_baseline(workload_name, min_seconds=10.0, max_reps=8):
         del u
     pts = float(np.prod(shape)) * reps
     return dict(value=round(pts / dt / 1e6, 3), unit="Mpts/s", cores=int(threads), kind="oracle",
-                sample=f"{reps} oracle solves of the {workload_name} recipe at 256^3 "
-                       f"({dt:.1f} s wall in total, float64 numpy, BLAS threads {threads})")
+                sample=f"{reps} oracle solves of the {workload_name} recipe on a {shape[2]} x {shape[1]} x "
+                       f"{shape[0]} slab (x, y lines as at full size; {dt:.1f} s wall in total, float64 numpy, "
+                       f"BLAS threads {threads})")
 
 
 def main():
@@ -218,8 +257,10 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 1 GiB device copies done")
         del a, b
-    copy_gbs = device_copy_bandwidth()
-    log(f"device copy (1 GiB read + 1 GiB write): {copy_gbs:.0f} GB/s")
+    copies = device_copy_bandwidth(lib)
+    copy_gbs = copies["stream_copy"]
+    log(f"device copy (1 GiB read + 1 GiB write): {copy_gbs:.0f} GB/s streaming kernel, "
+        f"{copies['torch_copy']:.0f} GB/s torch copy_")
 
     log(f"plan f64 {shape} {bc} batch {batch}")
     plan = Plan(shape, bc, h, dtype="f64", batch=batch)
@@ -249,6 +290,7 @@ def main():
                    "h": list(h)},
         "roofline": roofline_block(per, ab64, args.workload, "f64", shape[1]),
         "device_copy_GBs": round(copy_gbs, 1),
+        "torch_copy_GBs": round(copies["torch_copy"], 1),
         "solve_hbm_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
         "solve_hbm_frac": round(total_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         "kernels": kern,
@@ -318,16 +360,24 @@ def main():
         ms_r, _, per_r = time_solves(plan_r, f, ur, max(3, args.steps // 2), 2, lib)
         its, _, rel = plan_r.last_info()
         diff = float((ur - u).abs().max() / u.abs().max())
+        kern_r = {g: dict(per_r[g]) for g in GROUPS}
+        abr = refined_bytes(shape, batch, slots, its)
+        for g in abr:
+            if per_r[g]["total_ms"]:
+                # bytes of all launches of the group over their total time
+                kern_r[g]["algorithmic_GBs"] = round(abr[g] * per_r[g]["launches"] / (its + 1)
+                                                     / (per_r[g]["total_ms"] * 1e-3) / 1e9, 1)
         result["fp32_refined"] = {
             "value": round(npts / ms_r / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_r, 4),
             "refinement_steps": its, "last_rel_correction": rel, "max_rel_diff_vs_f64": diff,
-            "kernels": {g: dict(per_r[g]) for g in GROUPS},
+            "bytes_per_point": round(sum(abr.values()) / npts, 2),
+            "kernels": kern_r,
         }
         log(f"f32+refine: {ms_r:.3f} ms/solve, {its} corrections, diff vs f64 {diff:.2e}")
         del plan_r, ur
 
     if not args.skip_cpu_baseline:
-        log("timing the oracle on a 256^3 sample")
+        log("timing the oracle on a slab of the full grid")
         result["cpu_baseline"] = cpu_baseline(args.workload)
     result["context"] = {"paper_single_gpu_512cubed_Mpts_s": {"V100": 4.09, "K40": 1.56},
                          "note": "paper's multi-GPU code path on one GPU, boundary conditions unstated"}

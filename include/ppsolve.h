@@ -214,6 +214,14 @@ pp_status pp_plan_kernel_times(pp_plan p, double* ms, int* launches, int reset);
 #define PP_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
 pp_status pp_solve_noalloc(pp_plan p, const void* f, void* u, void* stream);
 
+/* Measurement utility, not part of the solve: copies `bytes` (a multiple of 16;
+ * src and dst 16-byte aligned, not overlapping) between device buffers with
+ * 16-byte non-temporal loads and stores over a persistent grid, on `stream`.
+ * Every kernel of the solve streams its input once and its output once, so the
+ * bandwidth of this copy is the practical ceiling their achieved bandwidth is
+ * compared with.  PP_ERR_ARG / PP_ERR_ALIAS / PP_ERR_HIP. */
+pp_status pp_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 void pp_plan_destroy(pp_plan p);
 
 /* Static, NUL-terminated description of a status code. */

@@ -27,7 +27,7 @@ EXPORTED = [
     "pp_plan_create", "pp_plan_set_gauge", "pp_plan_set_zsolver", "pp_plan_set_refinement",
     "pp_plan_workspace_bytes",
     "pp_solve", "pp_solve_bc", "pp_solve_adjoint", "pp_plan_last_info", "pp_plan_set_timing", "pp_plan_kernel_times",
-    "pp_plan_destroy", "pp_status_string", "pp_solve_noalloc",
+    "pp_plan_destroy", "pp_status_string", "pp_solve_noalloc", "pp_stream_copy",
 ]
 
 _lib = None
@@ -64,6 +64,8 @@ def load():
     lib.pp_solve.restype = i
     lib.pp_solve_bc.argtypes = [vp, vp, ctypes.POINTER(vp), vp, vp, vp]
     lib.pp_solve_bc.restype = i
+    lib.pp_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.pp_stream_copy.restype = i
     lib.pp_solve_noalloc.argtypes = [vp, vp, vp, vp]
     lib.pp_solve_noalloc.restype = i
     lib.pp_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]

@@ -197,6 +197,37 @@ template hipError_t launch_residual<double, double>(const double*, const double*
 template hipError_t launch_residual<double, float>(const double*, const double*, float*, const ResidualArgs&,
                                                    const double*, hipStream_t);
 
+// Streaming copy of n16 16-byte chunks: the bandwidth reference the solver's
+// kernels are measured against (every kernel of the solve streams its input once
+// and its output once).  Persistent grid, each thread moving kCopyUnroll chunks
+// per step with non-temporal loads and stores, all loads of a step issued before
+// its stores.
+constexpr int kCopyUnroll = 4;
+__global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                     size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kCopyUnroll - 1) * stride < n16; i += kCopyUnroll * stride) {
+        double2 v[kCopyUnroll];
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) v[k] = ld_stream(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) st_stream(dst + i + k * stride, v[k]);
+    }
+    for (; i < n16; i += stride) st_stream(dst + i, ld_stream(src + i));
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    hipLaunchKernelGGL(k_stream_copy, dim3(cus * 8), dim3(256), 0, s, reinterpret_cast<const double2*>(src),
+                       reinterpret_cast<double2*>(dst), bytes / 16);
+    return hipGetLastError();
+}
+
 // Set the scalars that the first (unrefined) float solve reads in update mode.
 __global__ void k_ir_init(double* sc, int batch) {
     const int t = threadIdx.x;

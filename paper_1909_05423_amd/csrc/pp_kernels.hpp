@@ -219,6 +219,9 @@ template <typename Tu, typename Tr>
 hipError_t launch_residual(const double* f, const Tu* u, Tr* r, const ResidualArgs& a,
                            const double* scalars, hipStream_t s);
 
+// Streaming device copy of `bytes` (a multiple of 16), the bandwidth reference.
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // Initial scalars of the refinement loop (unit scale, no gauge shift).
 hipError_t launch_ir_init(double* scalars, int batch, hipStream_t s);
 

@@ -69,3 +69,17 @@ def test_traffic_needs_counters_of_the_current_kernels(tmp_path, monkeypatch):
     f.write_text(json.dumps(dict(entry, kernel_source_hash=bench.kernel_source_hash())))
     assert bench.traffic_for("z_march", "w", "f64") == 123
     assert bench.traffic_for("x_forward", "w", "f64") is None
+
+
+def test_refined_bytes_512_one_correction():
+    # first solve 8 + 4 (x), 16 (z), 4 + 4 (x inverse to float u0); first
+    # correction 8 + 4 + 4 (fused residual), 16, 4 + 4 + 8: 84 B per point
+    n = 512 ** 3
+    rb = bench.refined_bytes((512, 512, 512), 1, 256, 1)
+    assert rb["x_forward"] == 28 * n
+    assert rb["z_march"] == 32 * n
+    assert rb["x_inverse"] == 24 * n
+    assert sum(rb.values()) == 84 * n
+    # each later correction: residual 24 B/pt + x transform 4 B/pt, march 16, update 20
+    rb2 = bench.refined_bytes((512, 512, 512), 1, 256, 2)
+    assert sum(rb2.values()) - sum(rb.values()) == (24 + 4 + 16 + 20) * n

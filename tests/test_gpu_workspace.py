@@ -125,3 +125,18 @@ def test_nonfinite_source_reported_every_dtype(dtype, bad):
         plan.last_info()
     assert ei.value.status == -8
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 48, (1 << 22) + 16 * 37])
+def test_stream_copy_copies(nbytes):
+    """The bandwidth reference copy (pp_stream_copy) moves every byte, tails included."""
+    import torch
+    from paper_1909_05423_amd import _lib
+    lib = _lib.load()
+    a = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    st = lib.pp_stream_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nbytes,
+                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

@@ -175,3 +175,14 @@ def test_noalloc_limit_matches_header():
     text = open(HEADER).read()
     m = re.search(r"#define PP_NOALLOC_SCRATCH_BYTES \((\d+)u \* 1024u \* 1024u\)", text)
     assert m and int(m.group(1)) * 1024 * 1024 == _lib.NOALLOC_SCRATCH_BYTES
+
+
+def test_stream_copy_argument_errors(lib):
+    """pp_stream_copy checks its arguments on the host (no GPU call for these)."""
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20)
+    assert lib.pp_stream_copy(None, b, 16, None) == -1
+    assert lib.pp_stream_copy(a, None, 16, None) == -1
+    assert lib.pp_stream_copy(a, b, 24, None) == -1                     # not a multiple of 16
+    assert lib.pp_stream_copy(ctypes.c_void_p(4104), b, 16, None) == -1  # misaligned source
+    assert lib.pp_stream_copy(a, ctypes.c_void_p(4096 + 16), 64, None) == -4   # overlap
+    assert lib.pp_stream_copy(a, b, 0, None) == 0
