@@ -177,6 +177,38 @@ def device_copy_bandwidth(lib, reps=10):
     return out
 
 
+def zsolver_sweep(lib, warmup, steps=10, bc="PPPPNN"):
+    """The paper's comparison of the tridiagonal solvers (section "Comparison of
+    Tridiagonal Solvers"): 64 x 64 x nz grids, nz = 2^n - 1 up to 4095, the
+    whole f64 solve timed with the fused Thomas march, PCR and CR-P (the last
+    two with the y transforms as separate passes).  Seeded N(0,1) source."""
+    import numpy as np
+    import torch
+    from paper_1909_05423_amd import Plan
+    rows = []
+    for nz in (255, 511, 1023, 2047, 4095):
+        shape = (nz, 64, 64)
+        h = (1 / 64, 1 / 64, 1 / nz)
+        f = torch.from_numpy(np.random.default_rng(nz).standard_normal((1,) + shape)).to("cuda")
+        u = torch.empty_like(f)
+        row = {"nz": nz}
+        ref = None
+        for key in ("thomas", "pcr", "cr"):
+            plan = Plan(shape, bc, h, dtype="f64", zsolver=key)
+            ms, _, _ = time_solves(plan, f, u, steps, warmup, lib)
+            row[f"{key}_ms"] = round(ms, 4)
+            if ref is None:
+                ref = u.clone()
+            else:
+                row[f"{key}_max_rel_diff_vs_thomas"] = float((u - ref).abs().max() / ref.abs().max())
+            del plan
+        rows.append(row)
+        log(f"64 x 64 x {nz}: Thomas {row['thomas_ms']:.3f} ms, PCR {row['pcr_ms']:.3f} ms, "
+            f"CR-P {row['cr_ms']:.3f} ms")
+        del f, u, ref
+    return {"shape": "64 x 64 x nz", "bc": bc, "dtype": "f64", "rows": rows}
+
+
 def cpu_baseline(workload_name, min_seconds=10.0, max_reps=8):
     """The oracle, timed on this host, on the same recipe on a 512 x 512 x 32
     slab of the 512^3 grid, repeated until about min_seconds of CPU work have
@@ -219,6 +251,8 @@ def main():
     ap.add_argument("--skip-faces", action="store_true", help="skip timing the solve with face values")
     ap.add_argument("--skip-periodic-z", action="store_true", help="skip timing the periodic-z solve")
     ap.add_argument("--skip-pcr", action="store_true", help="skip timing the PCR and CR-P z solvers")
+    ap.add_argument("--skip-sweep", action="store_true",
+                    help="skip the z-solver comparison on 64 x 64 x nz grids (the paper's sweep)")
     ap.add_argument("--skip-check", action="store_true", help="skip the host-side backward-error check")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) three times, as the reference "
@@ -353,6 +387,9 @@ def main():
             }
             log(f"f64 with {key.upper()} z solver: {ms_c:.3f} ms/solve")
             del plan_c, uc
+
+    if not args.skip_sweep:
+        result["zsolver_sweep"] = zsolver_sweep(lib, args.warmup)
 
     if not args.skip_refined:
         plan_r = Plan(shape, bc, h, dtype="f32_refined", batch=batch)

@@ -82,7 +82,8 @@ typedef enum {
  *               a slower general march);
  *   nz * batch  at most 65535 (launch grid of the refinement residual);
  *   periodic z  nz >= 3;
- *   PCR / CR-P  z not periodic (PP_ERR_BC), nz and ny at most 512 (set_zsolver).
+ *   PCR / CR-P  z not periodic (PP_ERR_BC), nz at most 4096 and ny at most 512
+ *               (set_zsolver).
  * Device workspace: pp_plan_workspace_bytes(p); about 8 B (PP_F64, and
  * PP_F32_REFINED; 16 B with rows over 512) or 4 B (PP_F32) per grid point and
  * batch entry, plus the plan tables. */
@@ -116,7 +117,7 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
  *                      the y transforms as separate passes (four passes);
  *   PP_ZSOLVER_CR      cyclic reduction with a parallel backward phase (CR-P),
  *                      arranged like PCR.
- *   PCR and CR-P: nz <= 512 and ny <= 512 (PP_ERR_SIZE otherwise), z not
+ *   PCR and CR-P: nz <= 4096 and ny <= 512 (PP_ERR_SIZE otherwise), z not
  *   periodic (PP_ERR_BC).  For comparison with the default. */
 typedef enum { PP_ZSOLVER_THOMAS = 0, PP_ZSOLVER_PCR = 1, PP_ZSOLVER_CR = 2 } pp_zsolver;
 pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);

@@ -1071,7 +1071,7 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver) {
     if (!p || (solver != PP_ZSOLVER_THOMAS && solver != PP_ZSOLVER_PCR && solver != PP_ZSOLVER_CR)) return PP_ERR_ARG;
     if (solver == PP_ZSOLVER_PCR || solver == PP_ZSOLVER_CR) {
         if (p->bz0 == pp::BC_P) return PP_ERR_BC;
-        if (p->nz > 512 || p->ny > 512) return PP_ERR_SIZE;
+        if (p->nz > 4096 || p->ny > 512) return PP_ERR_SIZE;
     }
     p->zsolver = (int)solver;
     if (p->dtype == PP_F32_REFINED) set_mixed_slots(p);

@@ -7,8 +7,8 @@
 // needs a whole y line of a plane, so this path runs them as separate passes
 // over the spectral array S:
 //   k_ypass<FWD>     y transform of every (slot, plane), in place;
-//   k_zpcr / k_zcr   PCR / CR-P along z for tiles of TE entries of one slot,
-//                    the whole line of each entry in LDS;
+//   k_zpcr / k_zcr   PCR / CR-P along z for tiles of real systems (the parts of
+//                    entries) of one slot, the whole line of each in LDS;
 //   k_ypass<INV>     inverse y transform, in place.
 // Two more HBM sweeps than the fused march (the point of the comparison).
 //
@@ -124,25 +124,248 @@ __global__ __launch_bounds__(512) void k_ypass(cplx<T>* __restrict__ S, MidArgs<
 }
 
 // ------------------------------------------------ PCR and CR-P along z
-// TE entries of one slot per 256-thread workgroup; LDS holds, per (entry, z),
-// the right-hand side x (complex: the real and imaginary parts are separate
-// systems) and the two off-diagonals of each part.  The reductions run in
-// double for either solve precision: their log2(nz) levels of combined rows
-// lose more to rounding than the Thomas recurrence does, which in float
-// exceeds the unrefined float tolerance on long lines.
+// The real and imaginary parts of an entry are independent systems.  Lines up
+// to 2048 rows use the paired layout below (k_zpcr2, k_zcr2); longer ones, up
+// to 4096, a 256-thread workgroup per real system ("part": part p of the tile
+// is entry e0 + p / 2, component p % 2; TP parts per tile, TP = 1 there), the
+// whole z line in LDS: per (z, part) the right-hand side x and the two
+// off-diagonals a, c (24 B, 98 KB at 4096 rows).  The
+// reductions run in double for either solve precision: their log2(nz) levels
+// of combined rows lose more to rounding than the Thomas recurrence does,
+// which in float exceeds the unrefined float tolerance on long lines.
 constexpr int kPcrThreads = 256;
-template <typename T> constexpr int pcr_te() { return 4; }
-template <typename T> constexpr size_t pcr_lds_bytes(int nz) {
-    return (size_t)pcr_te<T>() * nz * (sizeof(double2) + 4 * sizeof(double)) + 64 * sizeof(double);
+constexpr int kPcrPairRows = 2048;           // nz * TE per workgroup, paired layout
+constexpr int kPcrRowsMax = 4096;            // nz * TP per workgroup
+constexpr int kPcrItems = kPcrRowsMax / kPcrThreads;   // rows per thread (PCR registers)
+int pcr_parts(int nz) {
+    int tp = 8;
+    while (tp > 1 && nz * tp > kPcrRowsMax) tp >>= 1;
+    return tp;
+}
+size_t pcr_lds_bytes(int nz) { return (size_t)nz * pcr_parts(nz) * 3 * sizeof(double) + 64 * sizeof(double); }
+// paired layout: entries per tile (0: the line is too long for it)
+int pcr_entries(int nz) {
+    int te = 4;
+    while (te > 0 && nz * te > kPcrPairRows) te >>= 1;
+    return te;
+}
+size_t pcr2_lds_bytes(int nz) {
+    return (size_t)nz * pcr_entries(nz) * (sizeof(double2) + 4 * sizeof(double)) + 64 * sizeof(double);
 }
 
+// Load the tile's z lines of slot m into LDS (row r = z * TP + p), scaled and
+// normalised to a unit diagonal; the zero mode pinned (row 0: u_0 = 0, row 1
+// without its coupling to u_0).
+template <typename Tio>
+__device__ void tri_load(const cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int p0,
+                         int tp, double* X, double* A, double* C) {
+    using T = double;
+    const int nz = a.nz, ny = a.ny;
+    const bool sing = a.singular && m == 0;
+    const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
+    const T d0 = (a.bz0 == BC_D) ? T(-1) : T(1), d1 = (a.bz1 == BC_D) ? T(-1) : T(1);
+    // tp even: a thread reads one complex value and fills both parts' rows
+    const int cp = (tp & 1) ? 1 : 2;
+    const int nitems = nz * tp / cp;
+    for (int it = threadIdx.x; it < nitems; it += kPcrThreads)
+    for (int c2 = 0; c2 < cp; ++c2) {
+        const int r = it * cp + c2;
+        const int z = r / tp, pl = r - z * tp, pg = p0 + pl;
+        const int e = pg >> 1, comp = pg & 1;
+        T x = T(0), bm = T(1);
+        if (e < ny) {
+            const cplx<Tio> xs = S[base + (size_t)z * a.zstride + e];
+            const cplx<Tio> bs = a.bmid[(size_t)m * ny + e];
+            x = (T)(comp ? xs.y : xs.x) * (T)a.scale;
+            bm = (T)(comp ? bs.y : bs.x);
+        }
+        const bool pin = sing && e == 0 && comp == 0;   // the zero mode: row 0 reads u_0 = 0
+        if (pin) x -= proj;
+        T bd = bm;
+        if (z == 0) bd += d0;
+        if (z == nz - 1) bd += d1;
+        if (nz == 1) bd = bm + d0 + d1;
+        const T ib = T(1) / bd;
+        T av = (z > 0) ? ib : T(0);
+        T cv = (z < nz - 1) ? ib : T(0);
+        T xv = x * ib;
+        if (pin && z == 0) {
+            av = cv = T(0);
+            xv = T(0);
+        }
+        if (pin && z == 1) av = T(0);   // coupling to the pinned u_0 = 0
+        X[r] = xv;
+        A[r] = av;
+        C[r] = cv;
+    }
+}
+
+// Store the solved lines (each part into its component); the mean of the
+// zero-mode line for the zero-mean gauge.
+template <typename Tio>
+__device__ void tri_store(cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int p0,
+                          int tp, const double* X, double* red) {
+    const int nz = a.nz, ny = a.ny;
+    const bool sing = a.singular && m == 0;
+    double csum = 0.0;
+    if (!(tp & 1)) {
+        // whole complex values: parts 2q, 2q + 1 of a row are the entry's two components
+        for (int it = threadIdx.x; it < nz * tp / 2; it += kPcrThreads) {
+            const int r = 2 * it;
+            const int z = r / tp, pl = r - z * tp, e = (p0 + pl) >> 1;
+            if (e >= ny) continue;
+            S[base + (size_t)z * a.zstride + e] = mk<Tio>((Tio)X[r], (Tio)X[r + 1]);
+            if (sing && e == 0) csum += X[r];
+        }
+    } else {
+        Tio* Sr = reinterpret_cast<Tio*>(S);
+        for (int r = threadIdx.x; r < nz * tp; r += kPcrThreads) {
+            const int z = r / tp, pl = r - z * tp, pg = p0 + pl;
+            const int e = pg >> 1, comp = pg & 1;
+            if (e >= ny) continue;
+            const double u = X[r];
+            Sr[2 * (base + (size_t)z * a.zstride + e) + comp] = (Tio)u;
+            if (sing && e == 0 && comp == 0) csum += u;
+        }
+    }
+    if (m == 0 && blockIdx.x == 0) {
+        const double tot = block_sum<kPcrThreads>(csum, red);
+        if (threadIdx.x == 0) a.cmean[b] = (sing && a.demean) ? tot / (double)nz : 0.0;
+    }
+}
+
+template <typename Tio>
+__global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a, int tp) {
+    using T = double;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nz = a.nz;
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int p0 = blockIdx.x * tp;
+    const int tid = threadIdx.x;
+    const int nrows = nz * tp;
+    T* X = reinterpret_cast<T*>(smem);     // [z][tp]
+    T* A = X + nrows;
+    T* C = A + nrows;
+    double* red = C + nrows;
+    const size_t base = (size_t)b * a.slots * nz * a.ny + (size_t)m * a.sstride;
+    tri_load<Tio>(S, a, base, m, b, p0, tp, X, A, C);
+    __syncthreads();
+    for (int s = 1; s < nz; s <<= 1) {
+        T nx_[kPcrItems], na[kPcrItems], nc[kPcrItems];
+#pragma unroll
+        for (int k = 0; k < kPcrItems; ++k) {
+            const int r = tid + k * kPcrThreads;
+            if (r >= nrows) continue;
+            const int z = r / tp;
+            T am = T(0), cm = T(0), xm = T(0), ap = T(0), cp = T(0), xp = T(0);
+            if (z - s >= 0) {
+                am = A[r - s * tp];
+                cm = C[r - s * tp];
+                xm = X[r - s * tp];
+            }
+            if (z + s < nz) {
+                ap = A[r + s * tp];
+                cp = C[r + s * tp];
+                xp = X[r + s * tp];
+            }
+            const T ar = A[r], cr = C[r];
+            const T rr = T(1) / (T(1) - ar * cm - cr * ap);
+            na[k] = -rr * ar * am;
+            nc[k] = -rr * cr * cp;
+            nx_[k] = rr * (X[r] - ar * xm - cr * xp);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPcrItems; ++k) {
+            const int r = tid + k * kPcrThreads;
+            if (r >= nrows) continue;
+            A[r] = na[k];
+            C[r] = nc[k];
+            X[r] = nx_[k];
+        }
+        __syncthreads();
+    }
+    tri_store<Tio>(S, a, base, m, b, p0, tp, X, red);
+}
+
+// Cyclic reduction with a parallel backward phase (section "Cyclic Reduction
+// Technique", CR-P).  Forward: at stride s = 1, 2, 4, ... (while 2s <= nz) the
+// rows z = 2s-1, 4s-1, ... are combined with rows z -+ s as in PCR,
+//     r = 1 / (1 - a_z c_{z-s} - c_z a_{z+s})
+//     a_z <- -r a_z a_{z-s},  c_z <- -r c_z c_{z+s},
+//     x_z <- r (x_z - a_z x_{z-s} - c_z x_{z+s}),
+// which leaves them coupled to rows z -+ 2s only; the rows a level reads are
+// not the rows it writes, so a level needs one barrier.  The last stride s
+// leaves the single row s-1, already decoupled (x = u).  Backward: for
+// t = s/2, ..., 1 the rows z = t-1, 3t-1, ... take u_z = x_z - a_z u_{z-t} -
+// c_z u_{z+t}, their neighbours being solved at the coarser levels.  Rows
+// outside [0, nz) count as zero.
+template <typename Tio>
+__global__ __launch_bounds__(kPcrThreads) void k_zcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a, int tp) {
+    using T = double;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nz = a.nz;
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int p0 = blockIdx.x * tp;
+    const int tid = threadIdx.x;
+    const int nrows = nz * tp;
+    T* X = reinterpret_cast<T*>(smem);     // [z][tp]
+    T* A = X + nrows;
+    T* C = A + nrows;
+    double* red = C + nrows;
+    const size_t base = (size_t)b * a.slots * nz * a.ny + (size_t)m * a.sstride;
+    tri_load<Tio>(S, a, base, m, b, p0, tp, X, A, C);
+    __syncthreads();
+    int s = 1;
+    for (; 2 * s <= nz; s <<= 1) {
+        const int cnt = (nz - (2 * s - 1) + 2 * s - 1) / (2 * s);   // rows 2s-1 + 2s q < nz
+        for (int w = tid; w < cnt * tp; w += kPcrThreads) {
+            const int q = w / tp, pl = w - q * tp;
+            const int z = 2 * s - 1 + 2 * s * q;
+            const int r = z * tp + pl;
+            const T am = A[r - s * tp], cm = C[r - s * tp], xm = X[r - s * tp];   // z - s >= s - 1 >= 0
+            T ap = T(0), cp = T(0), xp = T(0);
+            if (z + s < nz) {
+                ap = A[r + s * tp];
+                cp = C[r + s * tp];
+                xp = X[r + s * tp];
+            }
+            const T ar = A[r], cr = C[r];
+            const T rr = T(1) / (T(1) - ar * cm - cr * ap);
+            X[r] = rr * (X[r] - ar * xm - cr * xp);
+            A[r] = -rr * ar * am;
+            C[r] = -rr * cr * cp;
+        }
+        __syncthreads();
+    }
+    // row s - 1 is decoupled: X already holds its solution
+    for (int t = s >> 1; t >= 1; t >>= 1) {
+        const int cnt = (nz - (t - 1) + 2 * t - 1) / (2 * t);         // rows t-1 + 2t q < nz
+        for (int w = tid; w < cnt * tp; w += kPcrThreads) {
+            const int q = w / tp, pl = w - q * tp;
+            const int z = t - 1 + 2 * t * q;
+            const int r = z * tp + pl;
+            const T um = (z - t >= 0) ? X[r - t * tp] : T(0);
+            const T up = (z + t < nz) ? X[r + t * tp] : T(0);
+            X[r] = X[r] - A[r] * um - C[r] * up;
+        }
+        __syncthreads();
+    }
+    tri_store<Tio>(S, a, base, m, b, p0, tp, X, red);
+}
+
+// Paired layout, for z lines up to 2048 (pcr_entries): both parts of TE entries
+// per tile, per (z, entry) the complex right-hand side and the off-diagonals of
+// the two parts (48 B), one thread per (z, entry) row working on both parts
+// with 16- and 32-byte LDS accesses.  (Splitting every tile into single parts
+// cost 30% at nz = 512: 6.0 -> 7.7 ms per PCR solve of 512^3.)
 // Load TE z lines of slot m into LDS (rows r = z * TE + el), scaled and
 // normalised to a unit diagonal; the zero mode pinned (row 0: u_0 = 0, row 1
 // without its coupling to u_0).  X[r] = right-hand side, AC[r] = (a.x, a.y,
 // c.x, c.y): lower and upper off-diagonals of the two parts.
-template <typename Tio, int TE>
-__device__ void tri_load(const cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int e0,
-                         cplx<double>* X, double* AC) {
+template <typename Tio>
+__device__ void tri_load2(const cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int e0,
+                          int TE, cplx<double>* X, double* AC) {
     using T = double;
     const int nz = a.nz, ny = a.ny;
     const bool sing = a.singular && m == 0;
@@ -184,9 +407,9 @@ __device__ void tri_load(const cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a,
 }
 
 // Store the solved lines; the mean of the zero-mode line for the zero-mean gauge.
-template <typename Tio, int TE>
-__device__ void tri_store(cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int e0,
-                          const cplx<double>* X, double* red) {
+template <typename Tio>
+__device__ void tri_store2(cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size_t base, int m, int b, int e0,
+                           int TE, const cplx<double>* X, double* red) {
     const int nz = a.nz, ny = a.ny;
     const bool sing = a.singular && m == 0;
     double csum = 0.0;
@@ -204,10 +427,9 @@ __device__ void tri_store(cplx<Tio>* __restrict__ S, const MidArgs<Tio>& a, size
 }
 
 template <typename Tio>
-__global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a) {
+__global__ __launch_bounds__(kPcrThreads) void k_zpcr2(cplx<Tio>* __restrict__ S, MidArgs<Tio> a, int TE) {
     using T = double;
-    constexpr int TE = pcr_te<Tio>();
-    constexpr int ITEMS = 512 * TE / kPcrThreads;   // (entry, z) rows per thread at nz = 512
+    constexpr int ITEMS = kPcrPairRows / kPcrThreads;   // (entry, z) rows per thread
     extern __shared__ __align__(16) unsigned char smem[];
     const int nz = a.nz;
     const int m = blockIdx.y, b = blockIdx.z;
@@ -218,7 +440,7 @@ __global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S,
     double* red = reinterpret_cast<double*>(AC + (size_t)nz * TE * 4);
     const size_t base = (size_t)b * a.slots * nz * a.ny + (size_t)m * a.sstride;
     const int nrows = nz * TE;
-    tri_load<Tio, TE>(S, a, base, m, b, e0, X, AC);
+    tri_load2<Tio>(S, a, base, m, b, e0, TE, X, AC);
     __syncthreads();
     for (int s = 1; s < nz; s <<= 1) {
         cplx<T> nx_[ITEMS];
@@ -271,7 +493,7 @@ __global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S,
         }
         __syncthreads();
     }
-    tri_store<Tio, TE>(S, a, base, m, b, e0, X, red);
+    tri_store2<Tio>(S, a, base, m, b, e0, TE, X, red);
 }
 
 // Cyclic reduction with a parallel backward phase (section "Cyclic Reduction
@@ -287,9 +509,8 @@ __global__ __launch_bounds__(kPcrThreads) void k_zpcr(cplx<Tio>* __restrict__ S,
 // c_z u_{z+t}, their neighbours being solved at the coarser levels.  Rows
 // outside [0, nz) count as zero.
 template <typename Tio>
-__global__ __launch_bounds__(kPcrThreads) void k_zcr(cplx<Tio>* __restrict__ S, MidArgs<Tio> a) {
+__global__ __launch_bounds__(kPcrThreads) void k_zcr2(cplx<Tio>* __restrict__ S, MidArgs<Tio> a, int TE) {
     using T = double;
-    constexpr int TE = pcr_te<Tio>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int nz = a.nz;
     const int m = blockIdx.y, b = blockIdx.z;
@@ -299,7 +520,7 @@ __global__ __launch_bounds__(kPcrThreads) void k_zcr(cplx<Tio>* __restrict__ S, 
     T* AC = reinterpret_cast<T*>(X + (size_t)nz * TE);         // [z][TE][4]: a.x, a.y, c.x, c.y
     double* red = reinterpret_cast<double*>(AC + (size_t)nz * TE * 4);
     const size_t base = (size_t)b * a.slots * nz * a.ny + (size_t)m * a.sstride;
-    tri_load<Tio, TE>(S, a, base, m, b, e0, X, AC);
+    tri_load2<Tio>(S, a, base, m, b, e0, TE, X, AC);
     __syncthreads();
     int s = 1;
     for (; 2 * s <= nz; s <<= 1) {
@@ -350,27 +571,43 @@ __global__ __launch_bounds__(kPcrThreads) void k_zcr(cplx<Tio>* __restrict__ S, 
         }
         __syncthreads();
     }
-    tri_store<Tio, TE>(S, a, base, m, b, e0, X, red);
+    tri_store2<Tio>(S, a, base, m, b, e0, TE, X, red);
 }
 
 // y passes around a reduction kernel on whole z lines: cr = false for PCR,
 // true for CR-P
 template <typename T>
 hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s, bool cr) {
+    if (a.nz > kPcrRowsMax || a.ny > 512) return hipErrorInvalidValue;
     const dim3 gy(a.slots, (a.nz + 7) / 8, batch);
     hipLaunchKernelGGL((k_ypass<T, false>), gy, dim3(512), 0, s, S, a);
-    const size_t lds = pcr_lds_bytes<T>(a.nz);
-    static bool attr = false;
+    static bool attr = false;   // once per process: the largest tile any plan asks for
     if (!attr) {
+        const int maxb = (int)((size_t)kPcrRowsMax * 3 * sizeof(double) + 64 * sizeof(double));
+        const int maxb2 = (int)((size_t)kPcrPairRows * (sizeof(double2) + 4 * sizeof(double)) + 64 * sizeof(double));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zpcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)pcr_lds_bytes<T>(512));
+                                  maxb);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)pcr_lds_bytes<T>(512));
+                                  maxb);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zpcr2<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, maxb2);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zcr2<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, maxb2);
         attr = true;
     }
-    const dim3 gz((a.ny + pcr_te<T>() - 1) / pcr_te<T>(), a.slots, batch);
-    if (cr) hipLaunchKernelGGL((k_zcr<T>), gz, dim3(kPcrThreads), lds, s, S, a);
-    else hipLaunchKernelGGL((k_zpcr<T>), gz, dim3(kPcrThreads), lds, s, S, a);
+    const int te = pcr_entries(a.nz);
+    if (te > 0) {
+        const dim3 gz((a.ny + te - 1) / te, a.slots, batch);
+        const size_t lds = pcr2_lds_bytes(a.nz);
+        if (cr) hipLaunchKernelGGL((k_zcr2<T>), gz, dim3(kPcrThreads), lds, s, S, a, te);
+        else hipLaunchKernelGGL((k_zpcr2<T>), gz, dim3(kPcrThreads), lds, s, S, a, te);
+    } else {
+        const int tp = pcr_parts(a.nz);
+        const dim3 gz((2 * a.ny + tp - 1) / tp, a.slots, batch);
+        const size_t lds = pcr_lds_bytes(a.nz);
+        if (cr) hipLaunchKernelGGL((k_zcr<T>), gz, dim3(kPcrThreads), lds, s, S, a, tp);
+        else hipLaunchKernelGGL((k_zpcr<T>), gz, dim3(kPcrThreads), lds, s, S, a, tp);
+    }
     hipLaunchKernelGGL((k_ypass<T, true>), gy, dim3(512), 0, s, S, a);
     return hipGetLastError();
 }

@@ -113,3 +113,27 @@ def test_pcr_with_faces_and_batch(zsolver):
         for b in range(2):
             fb = [None if g is None else g[b] for g in faces]
             assert rel_max(u[b], oracle.solve(f[b], bc, h, "mean", faces=fb)) < 1e-12, (bc, b)
+
+
+# The paper's comparison of the tridiagonal solvers runs 64 x 64 x nz grids
+# with nz = 2^n - 1 (the sizes CR-P is stated for) up to 4095 (section
+# "Comparison of Tridiagonal Solvers"); lines this long hold one real system
+# per workgroup tile.  Every solver against the oracle element by element.
+# Spacing h = 1/64 in every direction with a Dirichlet x direction: the
+# operator's condition number stays near 5e3 (on the unit cube, hz = 1/nz
+# makes it ~0.4 nz^2 = 7e6 at nz = 4095, where both the oracle's and any
+# double-precision solve's rounding errors reach 1e-11).
+@pytest.mark.parametrize("nz", [255, 511, 1023, 2047, 4095, 4096, 1000])
+@pytest.mark.parametrize("bc", ["DDDDDD", "DDNNNN", "DDPPND"])
+def test_paper_solver_sweep_shapes(nz, bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(nz + sum(map(ord, bc)))
+    shape = (nz, 64, 64)
+    h = (1 / 64, 1 / 64, 1 / 64)
+    f = rng.standard_normal(shape)
+    uo = oracle.solve(f, bc, h, "mean")
+    for zsolver in ["thomas", "pcr", "cr"]:
+        banner(f"sweep {zsolver} {bc} {shape}")
+        u, _ = _solve(f, bc, h, zsolver=zsolver)
+        err = rel_max(u, uo)
+        assert err < 1e-12, (zsolver, err)

@@ -145,8 +145,11 @@ def test_zsolver_option(lib):
         st, p = _create(lib, 8, 8, 8, "PPPPPP")
         assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -2     # periodic z: Thomas only
         lib.pp_plan_destroy(p)
-        st, p = _create(lib, 8, 8, 1024, "PPPPDD")
-        assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -3     # z lines longer than 512
+        st, p = _create(lib, 8, 8, 4096, "PPPPDD")
+        assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == 0      # z lines up to 4096
+        lib.pp_plan_destroy(p)
+        st, p = _create(lib, 8, 8, 4097, "PPPPDD")
+        assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -3     # z lines longer than 4096
         lib.pp_plan_destroy(p)
         st, p = _create(lib, 8, 1024, 8, "PPPPDD")
         assert st == 0 and lib.pp_plan_set_zsolver(p, solver) == -3     # y lines longer than 512
