@@ -86,7 +86,8 @@ typedef enum {
  *               (set_zsolver).
  * Device workspace: pp_plan_workspace_bytes(p); about 8 B (PP_F64, and
  * PP_F32_REFINED; 16 B with rows over 512) or 4 B (PP_F32) per grid point and
- * batch entry, plus the plan tables. */
+ * batch entry, plus the plan tables (and, for the split march below, two
+ * values per (x-wavenumber slot, y entry, batch entry)). */
 
 /* Create a plan (host only; no GPU call).
  *   nx, ny, nz  cells per direction, >= 1.  nx and ny must factor as 2^a 3^b.
@@ -113,6 +114,12 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
  * "Cyclic Reduction Technique", "Parallel Cyclic Reduction").
  *   PP_ZSOLVER_THOMAS  default: Thomas, fused with the y transforms in one
  *                      march along z (two passes over the spectral array).
+ *                      Non-periodic z with few columns (x-wavenumber slots
+ *                      times batch at most half the compute units) splits
+ *                      each z-system at a point near its middle: the upper
+ *                      part is eliminated from z = 0 and the lower part from
+ *                      z = nz-1 by two workgroups, which then solve the two
+ *                      meeting rows and substitute outward (same passes).
  *   PP_ZSOLVER_PCR     parallel cyclic reduction on whole z lines in LDS, with
  *                      the y transforms as separate passes (four passes);
  *   PP_ZSOLVER_CR      cyclic reduction with a parallel backward phase (CR-P),

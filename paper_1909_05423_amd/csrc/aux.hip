@@ -224,11 +224,7 @@ __global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__
 }
 
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-    }
+    const int cus = device_cus();
     hipLaunchKernelGGL(k_stream_copy, dim3(cus * 32), dim3(256), 0, s, reinterpret_cast<const double2*>(src),
                        reinterpret_cast<double2*>(dst), bytes / 16);
     return hipGetLastError();

@@ -33,6 +33,8 @@ struct Tables {
     size_t t_twx = 0, t_mkx = 0, t_twy = 0, t_mky = 0, t_rowoff = 0, t_lmax = 0, t_winf = 0, t_wlast = 0, t_wrows = 0;
     size_t t_elen = 0;
     size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
+    // split march: the lower half's pivots (by distance from the bottom row) and the meeting rows
+    size_t t_browoff = 0, t_belen = 0, t_bwinf = 0, t_bwrows = 0, t_meet = 0;
     // periodic z (Sherman-Morrison)
     size_t t_aelen = 0, t_qelen = 0;
     size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
@@ -62,6 +64,10 @@ struct pp_plan_s {
     Tables tb[2];
     int ntab = 1;
     int zsolver = 0;     // 0 Thomas (fused march), 1 PCR, 2 CR-P
+    // split march (non-periodic z, pipelined forms): first row of the lower
+    // half, a multiple of the march's chunk; 0 if the shape has no split form.
+    // Used when the columns alone would leave compute units idle.
+    int zsplit = 0;
     // refined solve: slots lo0 .. lo0+nlo-1 kept in double by the x transform and the z march
     int lo0 = 0, nlo = 0;
     // the first correction's size may stand for the refinement's contraction
@@ -71,6 +77,7 @@ struct pp_plan_s {
     // array; refined: o_r the float residual, o_u0 the float first solution,
     // o_lo the double slots
     size_t o_scalars = 0, o_partial = 0, o_tab[2] = {0, 0}, o_S = 0, o_r = 0, o_u0 = 0, o_lo = 0, ws_bytes = 0;
+    size_t o_zb[2] = {0, 0};   // split march: the halves' last eliminated values, per table set
     unsigned long long serial = 0;   // identifies the plan in the workspace registry
     // last call
     void* last_ws = nullptr;
@@ -252,8 +259,11 @@ template <typename T> void periodic_extras(double bmid, int nz, const std::vecto
     out->alpha.assign(al.begin(), al.begin() + La);
 }
 
+// krow >= 0: *wk = the reciprocal pivot of row krow in double (krow <= nz - 2;
+// the upper half's last row in a split march).
 template <typename T>
-void pivots(double lam, int nz, double hz, int bz0, int bz1, bool pinned, Line<T>* out) {
+void pivots(double lam, int nz, double hz, int bz0, int bz1, bool pinned, Line<T>* out, int krow = -1,
+            double* wk = nullptr) {
     const double bmid = -2.0 + hz * hz * lam;
     out->alpha.clear();
     out->qp.clear();
@@ -296,8 +306,38 @@ void pivots(double lam, int nz, double hz, int bz0, int bz1, bool pinned, Line<T
         prev = w;
     }
     const double wend = seq.back();  // value at index nz-2
+    if (krow >= 0 && wk) *wk = seq[std::min((size_t)krow, seq.size() - 1)];
     out->wlast = (T)(1.0 / ((bmid + d1) - wend));
     out->winf = (T)wend;
+    int L = (int)seq.size();
+    while (L > 0 && (T)seq[L - 1] == out->winf) --L;
+    out->tail = L;
+    out->body.resize(L);
+    for (int i = 0; i < L; ++i) out->body[i] = (T)seq[i];
+}
+
+// The lower half of a split march eliminates upward from the bottom face: the
+// same recurrence with the end rows exchanged, v_j the reciprocal pivot of row
+// nz-1-j for j = 0 .. jmax (stored up to convergence like the top-down
+// pivots); *vk = v_jmax in double (row zsplit).
+template <typename T> void bottom_pivots(double lam, int nz, double hz, int bz1, int jmax, Line<T>* out, double* vk) {
+    const double bmid = -2.0 + hz * hz * lam;
+    const double d1 = (bz1 == pp::BC_D) ? -1.0 : 1.0;
+    out->alpha.clear();
+    out->qp.clear();
+    std::vector<double> seq;
+    seq.reserve(64);
+    double prev = 1.0 / (bmid + d1);
+    seq.push_back(prev);
+    for (int j = 1; j <= jmax; ++j) {
+        const double v = 1.0 / (bmid - prev);
+        seq.push_back(v);
+        if (v == prev) break;   // fixed point
+        prev = v;
+    }
+    *vk = seq.back();
+    out->winf = (T)seq.back();
+    out->wlast = out->winf;
     int L = (int)seq.size();
     while (L > 0 && (T)seq[L - 1] == out->winf) --L;
     out->tail = L;
@@ -357,6 +397,12 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
     std::vector<int> rowoff(slots), lmax(slots), elen((size_t)slots * ny);
     std::vector<T> winf((size_t)slots * ny * 2), wlast((size_t)slots * ny * 2);
     std::vector<std::vector<Line<T>>> lines(slots);
+    // split march: the lower half's lines and, per (slot, entry, part), the
+    // meeting rows' pivots w (row zsplit-1, top-down), v (row zsplit,
+    // bottom-up) and 1 / (1 - v w), all from double
+    const int ks = p->zsplit;
+    std::vector<std::vector<Line<T>>> blines(ks > 0 ? slots : 0);
+    std::vector<T> meet(ks > 0 ? (size_t)slots * ny * 6 : 0);
     size_t rows = 0;
     for (int m = 0; m < slots; ++m) {
         const bool pairslot = (p->bx != pp::BC_P) || (m == 0);
@@ -374,6 +420,7 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
                     ky = (p->by == pp::BC_D) ? ny - 1 - e : e;  // DST entries are stored reversed
                 }
                 Line<T>& ln = lines[m][(size_t)e * 2 + part];
+                double wk = 0.0, vk = 0.0;
                 if (kx < 0) {
                     ln.body.clear();
                     ln.winf = 0;
@@ -381,7 +428,16 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
                     ln.tail = 0;
                 } else {
                     const bool pinned = p->singular && m == 0 && e == 0 && part == 0;
-                    pivots<T>(lamx[kx] + lamy[ky], nz, p->h[2], p->bz0, p->bz1, pinned, &ln);
+                    pivots<T>(lamx[kx] + lamy[ky], nz, p->h[2], p->bz0, p->bz1, pinned, &ln, ks - 1, &wk);
+                }
+                if (ks > 0) {
+                    if (blines[m].empty()) blines[m].resize((size_t)ny * 2);
+                    Line<T>& bl = blines[m][(size_t)e * 2 + part];
+                    if (kx >= 0) bottom_pivots<T>(lamx[kx] + lamy[ky], nz, p->h[2], p->bz1, nz - 1 - ks, &bl, &vk);
+                    T* mt = meet.data() + ((size_t)m * ny + e) * 6;
+                    mt[part] = (T)wk;
+                    mt[2 + part] = (T)vk;
+                    mt[4 + part] = (T)(1.0 / (1.0 - vk * wk));
                 }
                 winf[((size_t)m * ny + e) * 2 + part] = ln.winf;
                 wlast[((size_t)m * ny + e) * 2 + part] = ln.wlast;
@@ -420,6 +476,46 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
                 }
             }
         }
+    }
+    if (ks > 0) {
+        // the lower half's tables, laid out as the upper half's
+        std::vector<int> boff(slots), belen((size_t)slots * ny);
+        std::vector<T> bwinf((size_t)slots * ny * 2);
+        size_t brows = 0;
+        std::vector<int> blm(slots);
+        for (int m = 0; m < slots; ++m) {
+            int lm = 0;
+            for (int e = 0; e < ny; ++e) {
+                int el = 0;
+                for (int part = 0; part < 2; ++part) {
+                    const Line<T>& bl = blines[m][(size_t)e * 2 + part];
+                    bwinf[((size_t)m * ny + e) * 2 + part] = bl.winf;
+                    el = std::max(el, bl.tail);
+                }
+                belen[(size_t)m * ny + e] = el;
+                lm = std::max(lm, el);
+            }
+            boff[m] = (int)brows;
+            blm[m] = lm;
+            brows += lm;
+        }
+        tb.t_browoff = em.put(sizeof(int) * slots);
+        std::memcpy(tb.blob.data() + tb.t_browoff, boff.data(), sizeof(int) * slots);
+        tb.t_belen = em.put(sizeof(int) * belen.size());
+        std::memcpy(tb.blob.data() + tb.t_belen, belen.data(), sizeof(int) * belen.size());
+        tb.t_bwinf = em.put(sizeof(T) * bwinf.size());
+        std::memcpy(tb.blob.data() + tb.t_bwinf, bwinf.data(), sizeof(T) * bwinf.size());
+        tb.t_bwrows = em.put(sizeof(T) * 2 * std::max<size_t>(brows, 1) * ny);
+        T* bw = reinterpret_cast<T*>(tb.blob.data() + tb.t_bwrows);
+        for (int m = 0; m < slots; ++m)
+            for (int j = 0; j < blm[m]; ++j)
+                for (int e = 0; e < ny; ++e)
+                    for (int part = 0; part < 2; ++part) {
+                        const Line<T>& bl = blines[m][(size_t)e * 2 + part];
+                        bw[((size_t)(boff[m] + j) * ny + e) * 2 + part] = (j < bl.tail) ? bl.body[j] : bl.winf;
+                    }
+        tb.t_meet = em.put(sizeof(T) * meet.size());
+        std::memcpy(tb.blob.data() + tb.t_meet, meet.data(), sizeof(T) * meet.size());
     }
     // interior diagonal hz^2 lam - 2 of every z-system (PCR); padding parts get a
     // harmless non-singular value (their right-hand side is zero)
@@ -609,6 +705,18 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
     a.wrows = reinterpret_cast<const cplx<T>*>(t + tb.t_wrows);
     a.winf = reinterpret_cast<const cplx<T>*>(t + tb.t_winf);
     a.wlast = reinterpret_cast<const cplx<T>*>(t + tb.t_wlast);
+    // the split march where the columns alone would leave half the compute
+    // units or more without a workgroup
+    a.zsplit = 0;
+    if (p->zsplit > 0 && p->zsolver == 0 && 2 * (long long)p->slots * p->batch <= pp::device_cus()) {
+        a.zsplit = p->zsplit;
+        a.browoff = reinterpret_cast<const int*>(t + tb.t_browoff);
+        a.belen = reinterpret_cast<const int*>(t + tb.t_belen);
+        a.bwinf = reinterpret_cast<const cplx<T>*>(t + tb.t_bwinf);
+        a.bwrows = reinterpret_cast<const cplx<T>*>(t + tb.t_bwrows);
+        a.meet = reinterpret_cast<const cplx<T>*>(t + tb.t_meet);
+        a.zbuf = reinterpret_cast<cplx<T>*>(ws + p->o_zb[set]);
+    }
     a.zsolver = p->zsolver;
     a.bz0 = p->bz0;
     a.bz1 = p->bz1;
@@ -1029,6 +1137,13 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     // partial records per batch entry: one per (workgroup, wavefront) of the persistent
     // x kernels, whose grid never exceeds the row blocks of all batch entries
     p->nper = (size_t)((ny + p->ty - 1) / p->ty) * nz * batch * pp::kXWaves;
+    // split march: the meeting point on a chunk boundary near the middle (the
+    // refined solve's march has the float march's chunks)
+    {
+        const int kz = pp::zpipe_planes(ny, f64);
+        const int nch = kz > 0 ? (nz + kz - 1) / kz : 0;
+        if (p->bz0 != pp::BC_P && kz > 0 && nz >= 2 * kz) p->zsplit = kz * ((nch + 1) / 2);
+    }
     if (f64) build_tables<double>(p, p->tb[0]);
     else build_tables<float>(p, p->tb[0]);
     if (dtype == PP_F32_REFINED) {
@@ -1055,6 +1170,13 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     if (dtype == PP_F32_REFINED) off = align_up(off + sizeof(float) * n * batch);
     p->o_lo = off;
     off = align_up(off + sizeof(cplx<double>) * (size_t)batch * p->nlo * nz * ny);
+    if (p->zsplit > 0) {
+        for (int i = 0; i < p->ntab; ++i) {
+            p->o_zb[i] = off;
+            const size_t el = (i == 0) ? p->elem : sizeof(cplx<double>);
+            off = align_up(off + el * (size_t)batch * p->slots * 2 * ny);
+        }
+    }
     p->ws_bytes = off;
     *out = p;
     return PP_OK;

@@ -124,6 +124,17 @@ template <typename T> struct MidArgs {
     const cplx<T>* wrows;    // [row][ny] (w_re, w_im) reciprocal pivots
     const cplx<T>* winf;     // [slot][ny] converged reciprocal pivot
     const cplx<T>* wlast;    // [slot][ny] reciprocal pivot of the last row
+    // split march (non-periodic z): rows 0 .. zsplit-1 eliminated downward from
+    // z = 0 with the pivots above, rows zsplit .. nz-1 upward from z = nz-1 with
+    // the pivots of the reversed system (row nz-1-j at table row j); the two
+    // halves meet between rows zsplit-1 and zsplit.  zsplit 0: one march.
+    int zsplit;
+    const int* browoff;      // as rowoff / elen / wrows / winf, for the lower half
+    const int* belen;
+    const cplx<T>* bwrows;
+    const cplx<T>* bwinf;
+    const cplx<T>* meet;     // [slot][ny][3]: w of row zsplit-1, v of row zsplit, 1 / (1 - v w)
+    cplx<T>* zbuf;           // [batch][slot][2][ny]: last eliminated value of each half
     // periodic z (Sherman-Morrison, see the plan code): per slot, rows of
     // alpha = first row of the inverse of the split matrix and of the
     // forward-eliminated rank-one vector; per entry its last value, 1/den, 1/gamma
@@ -193,6 +204,13 @@ hipError_t launch_xinv_update(const cplx<float>* S, double* u, const float* upre
 
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s);
+
+// Compute units of the current device (256 if the query fails).
+int device_cus();
+// Planes per chunk of the pipelined z march for lines of ny in double or float
+// (0: no pipelined form, ny over 1024); the split march puts its meeting
+// point on a multiple of it.
+int zpipe_planes(int ny, bool dbl);
 
 // The refined solve's z stage: slots lo0 .. lo0+nlo-1 from their double
 // spectra Slo in double (tables of ad), the rest in float (tables of af); every

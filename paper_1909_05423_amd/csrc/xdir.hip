@@ -803,13 +803,18 @@ template <auto K> static void allow_lds() {
     }
 }
 
-// Persistent grid: a few resident workgroups per CU.
-int x_grid(int nblocks) {
+int device_cus() {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
+    return cus;
+}
+
+// Persistent grid: a few resident workgroups per CU.
+int x_grid(int nblocks) {
+    const int cus = device_cus();
     return nblocks < cus * kXBlocksPerCU ? nblocks : cus * kXBlocksPerCU;
 }
 

@@ -358,8 +358,17 @@ template <typename T, int NYMAX, int NW> struct ZpipeLds {
 // tables, a), Tf of the y transforms (LDS lines, tables af), Tout of everything
 // stored.  YFWD false: icol already holds the y-transformed values (k_ypre),
 // so the way up only eliminates (each thread prefetches its own entries).
-template <typename Tin, typename T, typename Tf, typename Tout, int NYMAX, int NW, bool FULL, bool PERZ, bool YFWD>
-__device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cplx<Tout>* ocol, size_t zs,
+//
+// PH 0: the whole march.  PH 1 and 2 split it between two workgroups per
+// column (blockIdx.z = 0: rows 0 .. zsplit-1 from z = 0; 1: rows zsplit ..
+// nz-1 from z = nz-1, through negated strides and the reversed system's
+// pivots).  PH 1 eliminates toward the meeting rows and leaves each half's
+// last eliminated value in zbuf; PH 2 solves the two meeting rows from them
+// and substitutes away from the meeting point.  Both halves run the same code
+// on their own rows, so the column has twice the workgroups in flight.
+template <typename Tin, typename T, typename Tf, typename Tout, int NYMAX, int NW, bool FULL, bool PERZ, bool YFWD,
+          int PH = 0>
+__device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs, cplx<Tout>* ocol, ptrdiff_t zs,
                                            const MidArgs<T>& a, const MidArgs<Tf>& af,
                                            ZpipeLds<Tf, NYMAX, NW>& L) {
     constexpr int NTH = 64 * NW;
@@ -373,7 +382,16 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     cplx<Tf>* mkl = L.mkl;
     const int m = blockIdx.x, b = blockIdx.y;
     const int ny = FULL ? NYMAX : a.ny;
-    const int nz = a.nz;
+    static_assert(PH == 0 || !PERZ, "periodic z is one march");
+    const int side = PH ? (int)blockIdx.z : 0;
+    const int nz = PH ? (side ? a.nz - a.zsplit : a.zsplit) : a.nz;   // rows of this march, in local order
+    if (side) {
+        icol += (ptrdiff_t)(a.nz - 1) * izs;
+        ocol += (ptrdiff_t)(a.nz - 1) * zs;
+        izs = -izs;
+        zs = -zs;
+    }
+    const cplx<T>* wrows = side ? a.bwrows : a.wrows;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -395,7 +413,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
     const bool sing = a.singular && (m == 0);
-    const int roff = a.rowoff[m];
+    const int roff = side ? a.browoff[m] : a.rowoff[m];
     const T scale = a.scale;
     const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
     const int half = (ny >> 1) + 1;
@@ -423,8 +441,8 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
         const int e = tid + NTH * o;
         live[o] = FULL || e < ny;
         ec[o] = live[o] ? e : 0;
-        winf[o] = a.winf[(size_t)m * ny + ec[o]];
-        elen[o] = a.elen[(size_t)m * ny + ec[o]];
+        winf[o] = (side ? a.bwinf : a.winf)[(size_t)m * ny + ec[o]];
+        elen[o] = (side ? a.belen : a.elen)[(size_t)m * ny + ec[o]];
         wlast[o] = a.wlast[(size_t)m * ny + ec[o]];
         y0[o] = mk<T>(T(0), T(0));
         corr[o] = y0[o];
@@ -456,7 +474,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
 #pragma unroll
             for (int o = 0; o < OWN; ++o) {
                 // lanes past their entry's rows read the same element (one cache line)
-                const cplx<T>* src = (z < elen[o]) ? a.wrows + (size_t)(roff + z) * ny + ec[o] : a.wrows;
+                const cplx<T>* src = (z < elen[o]) ? wrows + (size_t)(roff + z) * ny + ec[o] : wrows;
                 pv[l * OWN + o] = *src;
             }
         }
@@ -464,7 +482,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     // (component-wise selects between values, so that the arrays stay in registers)
     auto pivot = [&](int z, int l, int o) __attribute__((always_inline)) -> cplx<T> {
         const cplx<T> p = pv[l * OWN + o], wi = winf[o], wl = wlast[o];
-        const bool lastrow = (z == nz - 1), tab = (z < elen[o]);
+        const bool lastrow = (PH == 0) && (z == nz - 1), tab = (z < elen[o]);
         return mk<T>(lastrow ? wl.x : (tab ? p.x : wi.x), lastrow ? wl.y : (tab ? p.y : wi.y));
     };
     // upward prefetch (clamped to the last plane): YFWD, elements y = lane + 64 k
@@ -472,7 +490,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     cplx<T> pre[EPL];
     auto load_plane = [&](int zc) __attribute__((always_inline)) {
         if constexpr (YFWD) {
-            const cplx<Tin>* src = icol + (size_t)min(zc + wave, nz - 1) * izs;
+            const cplx<Tin>* src = icol + (ptrdiff_t)min(zc + wave, nz - 1) * izs;
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 const int y = lane + 64 * k;
@@ -483,7 +501,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
             for (int l = 0; l < kSZ; ++l) {
 #pragma unroll
                 for (int o = 0; o < OWN; ++o)
-                    pre[l * OWN + o] = cvt<T>(icol[(size_t)min(zc + l, nz - 1) * izs + ec[o]]);
+                    pre[l * OWN + o] = cvt<T>(icol[(ptrdiff_t)min(zc + l, nz - 1) * izs + ec[o]]);
             }
         }
     };
@@ -492,7 +510,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
 #pragma unroll
         for (int l = 0; l < kSZ; ++l) {
 #pragma unroll
-            for (int o = 0; o < OWN; ++o) pre[l * OWN + o] = cvt<T>(ocol[(size_t)min(zc + l, nz - 1) * zs + ec[o]]);
+            for (int o = 0; o < OWN; ++o) pre[l * OWN + o] = cvt<T>(ocol[(ptrdiff_t)min(zc + l, nz - 1) * zs + ec[o]]);
         }
     };
 
@@ -500,8 +518,10 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     cplx<T> st[OWN];
 #pragma unroll
     for (int o = 0; o < OWN; ++o) st[o] = mk<T>(T(0), T(0));
-    load_plane(0);
-    load_piv(0);
+    if constexpr (PH != 2) {
+        load_plane(0);
+        load_piv(0);
+    }
     auto up_chunk = [&](int c) __attribute__((always_inline)) {
         const int zc = c * kSZ;
         const int nl = FULL ? kSZ : min(kSZ, nz - zc);
@@ -612,7 +632,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
                         }
                     }
                     prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
-                    ocol[(size_t)z * zs + e] = cvt<Tout>(prev);
+                    ocol[(ptrdiff_t)z * zs + e] = cvt<Tout>(prev);
                 }
             }
             st[o] = prev;
@@ -621,12 +641,23 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     };
     // the first chunk is issued outside the loop so that every pass through the
     // loop sees the same sequence of memory operations before it
-    up_chunk(0);
-    for (int c = 1; c < nchunks; ++c) up_chunk(c);
+    if constexpr (PH != 2) {
+        up_chunk(0);
+        for (int c = 1; c < nchunks; ++c) up_chunk(c);
+    }
+    if constexpr (PH == 1) {
+        // this half's last eliminated values, for the meeting rows
+#pragma unroll
+        for (int o = 0; o < OWN; ++o)
+            if (live[o]) a.zbuf[(((size_t)b * a.slots + m) * 2 + side) * ny + ec[o]] = st[o];
+        if (side == 0 && m == 0 && tid == 0) a.cmean[b] = 0.0;   // the halves add their shares in PH 2
+        return;
+    }
 
     // ----------------------------------------------------------- downward
     // the top chunk's eliminated right-hand sides were stored by this thread
     // (same entries, same addresses): read them back in program order
+    if constexpr (PH == 2) load_piv(last);
     load_entry(last);
 #pragma unroll
     for (int o = 0; o < OWN; ++o) {
@@ -635,7 +666,20 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
             const cplx<T> ig = a.inv_gamma[(size_t)m * ny + ec[o]], id = a.inv_den[(size_t)m * ny + ec[o]];
             corr[o] = mk<T>((y0[o].x + st[o].x * ig.x) * id.x, (y0[o].y + st[o].y * ig.y) * id.y);
         }
-        st[o] = mk<T>(T(0), T(0));
+        if constexpr (PH == 2) {
+            // the meeting rows k-1 and k from the halves' last eliminated values
+            // (upper yu = y_{k-1}, lower yl = y'_k): u_{k-1} = yu - w u_k and
+            // u_k = yl - v u_{k-1}; each half starts from its neighbour across
+            // the meeting point, g = 1 / (1 - v w)
+            const size_t zb = ((size_t)b * a.slots + m) * 2 * ny + ec[o];
+            const cplx<T> yu = a.zbuf[zb], yl = a.zbuf[zb + ny];
+            const cplx<T>* mt = a.meet + ((size_t)m * ny + ec[o]) * 3;
+            const cplx<T> w = mt[0], v = mt[1], g = mt[2];
+            st[o] = side ? mk<T>(g.x * (yu.x - w.x * yl.x), g.y * (yu.y - w.y * yl.y))
+                         : mk<T>(g.x * (yl.x - v.x * yu.x), g.y * (yl.y - v.y * yu.y));
+        } else {
+            st[o] = mk<T>(T(0), T(0));
+        }
     }
     double csum = 0.0;
     auto down_chunk = [&](int c) __attribute__((always_inline)) {
@@ -707,7 +751,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
                 }
             }
             wave_lds_sync();
-            cplx<Tout>* dst = ocol + (size_t)(zc + wave) * zs;
+            cplx<Tout>* dst = ocol + (ptrdiff_t)(zc + wave) * zs;
             if (reg512) {
                 cplx<Tf> v[EPL];
                 if constexpr (R512) {
@@ -735,15 +779,19 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, size_t izs, cp
     };
     down_chunk(nchunks - 1);
     for (int c = nchunks - 2; c >= 0; --c) down_chunk(c);
-    if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
+    if constexpr (PH == 2) {
+        if (m == 0 && tid == 0 && sing && a.demean) atomicAdd(&a.cmean[b], csum / (double)a.nz);
+    } else {
+        if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
+    }
 }
 
 // The march in one precision, in place.
-template <typename T, int NYMAX, int NW, bool FULL, bool PERZ>
+template <typename T, int NYMAX, int NW, bool FULL, bool PERZ, int PH>
 __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
     __shared__ __align__(16) ZpipeLds<T, NYMAX, NW> L;
     cplx<T>* col = S + (size_t)blockIdx.y * a.slots * a.nz * a.ny + (size_t)blockIdx.x * a.sstride;
-    zpipe_body<T, T, T, T, NYMAX, NW, FULL, PERZ, true>(col, (size_t)a.zstride, col, (size_t)a.zstride, a, a, L);
+    zpipe_body<T, T, T, T, NYMAX, NW, FULL, PERZ, true, PH>(col, a.zstride, col, a.zstride, a, a, L);
 }
 
 // The refined solve's march: slots lo0 .. lo0+nlo-1 (the smallest x
@@ -754,7 +802,7 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
 // branch is uniform over the workgroup.  (Doing the double slots' y transforms
 // here instead made those workgroups the last to finish: 0.69 against 0.52 ms
 // at 512^3.)
-template <int NYMAX, int NW, bool FULL, bool PERZ>
+template <int NYMAX, int NW, bool FULL, bool PERZ, int PH>
 __global__ __launch_bounds__(64 * NW) void k_zpipe_mixed(const cplx<double>* __restrict__ Slo,
                                                          cplx<float>* __restrict__ S, MidArgs<double> ad,
                                                          MidArgs<float> af, int lo0, int nlo) {
@@ -763,11 +811,11 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe_mixed(const cplx<double>* __r
     cplx<float>* col = S + (size_t)blockIdx.y * af.slots * af.nz * af.ny + (size_t)blockIdx.x * af.sstride;
     if (k >= 0 && k < nlo) {
         const cplx<double>* icol = Slo + ((size_t)blockIdx.y * af.nz * nlo + k) * af.ny;
-        zpipe_body<double, double, float, float, NYMAX, NW, FULL, PERZ, false>(icol, (size_t)nlo * af.ny, col,
-                                                                               (size_t)af.zstride, ad, af, L);
+        zpipe_body<double, double, float, float, NYMAX, NW, FULL, PERZ, false, PH>(icol, (ptrdiff_t)nlo * af.ny, col,
+                                                                                   af.zstride, ad, af, L);
     } else {
-        zpipe_body<float, float, float, float, NYMAX, NW, FULL, PERZ, true>(col, (size_t)af.zstride, col,
-                                                                            (size_t)af.zstride, af, af, L);
+        zpipe_body<float, float, float, float, NYMAX, NW, FULL, PERZ, true, PH>(col, af.zstride, col, af.zstride, af,
+                                                                                af, L);
     }
 }
 
@@ -835,17 +883,33 @@ __global__ __launch_bounds__(64 * kYpreWaves) void k_ypre(cplx<double>* __restri
     for (int y = lane; y < ny; y += 64) src[y] = line[pad(y)];
 }
 
+// Every chunk of the march (of both halves, when split) whole.
+template <typename T> static bool pipe_full(const MidArgs<T>& a, int nymax, int nw) {
+    if (a.ny != nymax) return false;
+    if (a.zsplit > 0) return a.zsplit % nw == 0 && (a.nz - a.zsplit) % nw == 0;
+    return a.nz % nw == 0;
+}
+
 template <typename T, int NYMAX, int NW, bool FULL>
 static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    const dim3 grid(a.slots, batch), block(64 * NW);
-    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, true>), grid, block, 0, s, S, a);
-    else hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false>), grid, block, 0, s, S, a);
+    const dim3 block(64 * NW);
+    if (a.zsplit > 0) {   // never with periodic z
+        const dim3 grid(a.slots, batch, 2);
+        hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 1>), grid, block, 0, s, S, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 2>), grid, block, 0, s, S, a);
+        return hipGetLastError();
+    }
+    const dim3 grid(a.slots, batch);
+    if (a.zper) hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, true, 0>), grid, block, 0, s, S, a);
+    else hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 0>), grid, block, 0, s, S, a);
     return hipGetLastError();
 }
 
 template <typename T, int NYMAX, int NW>
 static hipError_t launch_pipe_any(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
-    if (a.ny == NYMAX && a.nz % NW == 0) return launch_pipe<T, NYMAX, NW, true>(S, a, batch, s);
+    if (pipe_full(a, NYMAX, NW)) return launch_pipe<T, NYMAX, NW, true>(S, a, batch, s);
     return launch_pipe<T, NYMAX, NW, false>(S, a, batch, s);
 }
 
@@ -884,11 +948,20 @@ hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s)
 template <int NYMAX, int NW, bool FULL>
 static hipError_t launch_mixed(const cplx<double>* Slo, cplx<float>* S, const MidArgs<double>& ad,
                                const MidArgs<float>& af, int lo0, int nlo, int batch, hipStream_t s) {
-    const dim3 grid(af.slots, batch), block(64 * NW);
+    const dim3 block(64 * NW);
+    if (af.zsplit > 0) {   // never with periodic z
+        const dim3 grid(af.slots, batch, 2);
+        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, false, 1>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, false, 2>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
+        return hipGetLastError();
+    }
+    const dim3 grid(af.slots, batch);
     if (af.zper)
-        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, true>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
+        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, true, 0>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
     else
-        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, false>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
+        hipLaunchKernelGGL((k_zpipe_mixed<NYMAX, NW, FULL, false, 0>), grid, block, 0, s, Slo, S, ad, af, lo0, nlo);
     return hipGetLastError();
 }
 
@@ -907,11 +980,17 @@ hipError_t launch_mid_mixed(const cplx<double>* Slo, cplx<float>* S, const MidAr
         if (e != hipSuccess) return e;
     }
     if (af.ny == 384) {
-        if (af.nz % 6 == 0) return launch_mixed<384, 6, true>(Slo, S, ad, af, lo0, nlo, batch, s);
+        if (pipe_full(af, 384, 6)) return launch_mixed<384, 6, true>(Slo, S, ad, af, lo0, nlo, batch, s);
         return launch_mixed<384, 6, false>(Slo, S, ad, af, lo0, nlo, batch, s);
     }
-    if (af.ny == 512 && af.nz % 8 == 0) return launch_mixed<512, 8, true>(Slo, S, ad, af, lo0, nlo, batch, s);
+    if (pipe_full(af, 512, 8)) return launch_mixed<512, 8, true>(Slo, S, ad, af, lo0, nlo, batch, s);
     return launch_mixed<512, 8, false>(Slo, S, ad, af, lo0, nlo, batch, s);
+}
+
+int zpipe_planes(int ny, bool dbl) {
+    if (ny > 1024) return 0;
+    if (!dbl && ny == 384) return 6;
+    return (dbl && ny > 512) ? 4 : 8;
 }
 
 template hipError_t launch_mid<double>(cplx<double>*, const MidArgs<double>&, int, hipStream_t);
