@@ -114,8 +114,7 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
  * "Cyclic Reduction Technique", "Parallel Cyclic Reduction").
  *   PP_ZSOLVER_THOMAS  default: Thomas, fused with the y transforms in one
  *                      march along z (two passes over the spectral array).
- *                      Non-periodic z with few columns (x-wavenumber slots
- *                      times batch at most half the compute units) splits
+ *                      Non-periodic z with few columns (see pp_zsplit) splits
  *                      each z-system at a point near its middle: the upper
  *                      part is eliminated from z = 0 and the lower part from
  *                      z = nz-1 by two workgroups, which then solve the two
@@ -128,6 +127,20 @@ pp_status pp_plan_set_gauge(pp_plan p, pp_gauge gauge);
  *   periodic (PP_ERR_BC).  For comparison with the default. */
 typedef enum { PP_ZSOLVER_THOMAS = 0, PP_ZSOLVER_PCR = 1, PP_ZSOLVER_CR = 2 } pp_zsolver;
 pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
+
+/* Layout of the Thomas march (PP_ZSOLVER_THOMAS; the other solvers ignore it).
+ *   PP_ZSPLIT_AUTO  default: split where the columns (x-wavenumber slots times
+ *                   batch) are at most 1/2 (PP_F64), 2 (PP_F32) or 4
+ *                   (PP_F32_REFINED) per compute unit of the device;
+ *   PP_ZSPLIT_OFF   always one workgroup per column;
+ *   PP_ZSPLIT_ON    always split (two workgroups per column).
+ * The split form exists for non-periodic z, y lines up to 1024 and nz of at
+ * least two chunks of the march (16 planes; 12 for float lines of 384, 8 for
+ * double lines over 512): PP_ZSPLIT_ON on other shapes returns PP_ERR_BC
+ * (periodic z) or PP_ERR_SIZE.  Both layouts compute the same elimination up
+ * to the order of its rounding. */
+typedef enum { PP_ZSPLIT_AUTO = 0, PP_ZSPLIT_OFF = 1, PP_ZSPLIT_ON = 2 } pp_zsplit;
+pp_status pp_plan_set_zsplit(pp_plan p, pp_zsplit mode);
 
 /* Refinement controls for PP_F32_REFINED: stop once the estimated relative
  * error of u (max-norm) is at most tol, or after max_iter correction steps

@@ -24,7 +24,7 @@ STATUS = {
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 EXPORTED = [
-    "pp_plan_create", "pp_plan_set_gauge", "pp_plan_set_zsolver", "pp_plan_set_refinement",
+    "pp_plan_create", "pp_plan_set_gauge", "pp_plan_set_zsolver", "pp_plan_set_zsplit", "pp_plan_set_refinement",
     "pp_plan_workspace_bytes",
     "pp_solve", "pp_solve_bc", "pp_solve_adjoint", "pp_plan_last_info", "pp_plan_set_timing", "pp_plan_kernel_times",
     "pp_plan_destroy", "pp_status_string", "pp_solve_noalloc", "pp_stream_copy",
@@ -56,6 +56,8 @@ def load():
     lib.pp_plan_set_gauge.restype = i
     lib.pp_plan_set_zsolver.argtypes = [vp, i]
     lib.pp_plan_set_zsolver.restype = i
+    lib.pp_plan_set_zsplit.argtypes = [vp, i]
+    lib.pp_plan_set_zsplit.restype = i
     lib.pp_plan_set_refinement.argtypes = [vp, d, i]
     lib.pp_plan_set_refinement.restype = i
     lib.pp_plan_workspace_bytes.argtypes = [vp]

@@ -68,6 +68,7 @@ struct pp_plan_s {
     // half, a multiple of the march's chunk; 0 if the shape has no split form.
     // Used when the columns alone would leave compute units idle.
     int zsplit = 0;
+    int zsplit_mode = 0;   // pp_zsplit
     // refined solve: slots lo0 .. lo0+nlo-1 kept in double by the x transform and the z march
     int lo0 = 0, nlo = 0;
     // the first correction's size may stand for the refinement's contraction
@@ -707,8 +708,17 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
     a.wlast = reinterpret_cast<const cplx<T>*>(t + tb.t_wlast);
     // the split march where the columns alone would leave half the compute
     // units or more without a workgroup
+    // automatic, by columns (slots x batch) per compute unit, as measured:
+    // double at most 1/2 (one workgroup per CU either way: 256^3 with 128
+    // columns 0.31 -> 0.18 ms; 193 or 256 columns 2-5% slower split); float at
+    // most 2 (the halves run two per CU: 512^3 0.53 -> 0.44 ms, 1024^2 x 512
+    // 2.50 -> 2.36 ms; 772 columns 11% slower); the refined solve's mixed
+    // march at most 4 (772 columns of 384^3 x 4: 1.61 -> 1.30 ms)
     a.zsplit = 0;
-    if (p->zsplit > 0 && p->zsolver == 0 && 2 * (long long)p->slots * p->batch <= pp::device_cus()) {
+    const long long cols = (long long)p->slots * p->batch, cus = pp::device_cus();
+    const long long lim = p->dtype == PP_F64 ? cus / 2 : (p->dtype == PP_F32 ? 2 * cus : 4 * cus);
+    const bool split = p->zsplit_mode == PP_ZSPLIT_ON || (p->zsplit_mode == PP_ZSPLIT_AUTO && cols <= lim);
+    if (p->zsplit > 0 && p->zsolver == 0 && split) {
         a.zsplit = p->zsplit;
         a.browoff = reinterpret_cast<const int*>(t + tb.t_browoff);
         a.belen = reinterpret_cast<const int*>(t + tb.t_belen);
@@ -790,6 +800,7 @@ pp_status run_plain(pp_plan p, const Tio* f, Tio* u, unsigned char* ws, hipStrea
                     const pp::FaceArgs<Tio>* faces) {
     pp::XArgs<T> xa = make_xargs<T>(p, ws);
     pp::MidArgs<T> ma = make_midargs<T>(p, ws, project, demean);
+    xa.zends = ma.zsplit > 0;
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
     double* partial = reinterpret_cast<double*>(ws + p->o_partial);
     cplx<T>* S = reinterpret_cast<cplx<T>*>(ws + p->o_S);
@@ -836,6 +847,7 @@ pp_status run_refined(pp_plan p, const double* f, double* u, unsigned char* ws, 
     pp::XArgs<float> xa = make_xargs<float>(p, ws, 0);       // inverse: float
     pp::MidArgs<float> ma = make_midargs<float>(p, ws, project, demean, 0);
     pp::MidArgs<double> ma64 = make_midargs<double>(p, ws, project, demean, 1);
+    xa.zends = ma.zsplit > 0;
     double* sc = reinterpret_cast<double*>(ws + p->o_scalars);
     double* partial = reinterpret_cast<double*>(ws + p->o_partial);
     cplx<float>* S = reinterpret_cast<cplx<float>*>(ws + p->o_S);
@@ -1197,6 +1209,13 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver) {
     }
     p->zsolver = (int)solver;
     if (p->dtype == PP_F32_REFINED) set_mixed_slots(p);
+    return PP_OK;
+}
+
+pp_status pp_plan_set_zsplit(pp_plan p, pp_zsplit mode) {
+    if (!p || (mode != PP_ZSPLIT_AUTO && mode != PP_ZSPLIT_OFF && mode != PP_ZSPLIT_ON)) return PP_ERR_ARG;
+    if (mode == PP_ZSPLIT_ON && p->zsplit == 0) return (p->bz0 == pp::BC_P) ? PP_ERR_BC : PP_ERR_SIZE;
+    p->zsplit_mode = (int)mode;
     return PP_OK;
 }
 

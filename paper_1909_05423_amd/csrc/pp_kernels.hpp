@@ -62,6 +62,10 @@ template <typename T> struct XArgs {
     int fbc[6];              // face types (Bc), x-, x+, y-, y+, z-, z+
     int proj;
     double ihx2, ihy2, ihz2;
+    // inverse kernels: take the z planes of each batch entry from both ends
+    // inward (0, nz-1, 1, nz-2, ...), the order in which the split z march
+    // finishes them, so that the most recently written planes are read first
+    int zends;
 };
 
 // Non-homogeneous face values, faces in the order x-, x+, y-, y+, z-, z+.  The

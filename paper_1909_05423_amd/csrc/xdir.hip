@@ -61,12 +61,14 @@ template <bool PAIR> __device__ __forceinline__ int x_next_block(int blk) {
     else return blk + (int)gridDim.x;
 }
 
-__device__ __forceinline__ XBlock x_block(int blk, int nyb, int nz, int ty) {
+// ends: z planes from both ends inward (XArgs::zends)
+__device__ __forceinline__ XBlock x_block(int blk, int nyb, int nz, int ty, bool ends = false) {
     XBlock r;
     const int yb = blk % nyb;
     const int zz = blk / nyb;
+    const int q = zz % nz;
     r.y0 = yb * ty;
-    r.z = zz % nz;
+    r.z = ends ? ((q & 1) ? nz - 1 - (q >> 1) : (q >> 1)) : q;
     r.b = zz / nz;
     return r;
 }
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
 
     cplx<T> sa[PAIRS], sb[PAIRS];
     auto fetch = [&](int blk) {
-        const XBlock xb = x_block(blk, nyb, nz, ty);
+        const XBlock xb = x_block(blk, nyb, nz, ty, a.zends);
         const cplx<T>* srcS = S + (size_t)xb.b * a.slots * nz * ny;
 #pragma unroll
         for (int k = 0; k < PAIRS; ++k) {
@@ -638,7 +640,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(const cplx<T>* __restrict__ S, Tou
     for (int r = 0; r < UR; ++r) uo[r] = 0.0;
 
     auto step = [&](int blk) {
-        const XBlock xb = x_block(blk, nyb, nz, ty);
+        const XBlock xb = x_block(blk, nyb, nz, ty, a.zends);
         if (xb.b != cur_b) {
             flush();
             cur_b = xb.b;

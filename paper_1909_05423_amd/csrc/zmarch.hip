@@ -403,9 +403,12 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     // last (inverse) stage in registers (w512_*)
     constexpr bool R512 = FULL && NYMAX == 512;
     const bool reg512 = R512 && a.by == BC_P;
-    using Tw512 = std::conditional_t<sizeof(Tf) == 4, Tw512Reg<Tf>, Tw512Lds<Tf>>;
+    // (float twiddles in registers in the whole march; the split march's
+    // halves read them from LDS, to fit two workgroups per CU)
+    constexpr bool TWREG = sizeof(Tf) == 4 && PH == 0;
+    using Tw512 = std::conditional_t<TWREG, Tw512Reg<Tf>, Tw512Lds<Tf>>;
     Tw512 w512;
-    if constexpr (sizeof(Tf) == 4) {
+    if constexpr (TWREG) {
         if constexpr (R512) w512 = tw512_regs<Tf>(af.twy, lane);
     } else {
         w512 = Tw512Lds<Tf>{twl, lane};
@@ -786,9 +789,17 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     }
 }
 
+// Waves per SIMD a march kernel is compiled for: the split march's halves in
+// float on lines up to 512 at 4 (at most 128 VGPRs: two 512-thread
+// workgroups per CU; 512^3 float march 0.51 -> 0.46 ms), everything else at 1
+// (the registers it needs).
+template <typename T, int NYMAX, int PH> constexpr int zpipe_min_waves() {
+    return (PH != 0 && sizeof(T) == 4 && NYMAX <= 512) ? 4 : 1;
+}
+
 // The march in one precision, in place.
 template <typename T, int NYMAX, int NW, bool FULL, bool PERZ, int PH>
-__global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
+__global__ __launch_bounds__(64 * NW, (zpipe_min_waves<T, NYMAX, PH>())) void k_zpipe(cplx<T>* __restrict__ S, MidArgs<T> a) {
     __shared__ __align__(16) ZpipeLds<T, NYMAX, NW> L;
     cplx<T>* col = S + (size_t)blockIdx.y * a.slots * a.nz * a.ny + (size_t)blockIdx.x * a.sstride;
     zpipe_body<T, T, T, T, NYMAX, NW, FULL, PERZ, true, PH>(col, a.zstride, col, a.zstride, a, a, L);
@@ -802,8 +813,9 @@ __global__ __launch_bounds__(64 * NW) void k_zpipe(cplx<T>* __restrict__ S, MidA
 // branch is uniform over the workgroup.  (Doing the double slots' y transforms
 // here instead made those workgroups the last to finish: 0.69 against 0.52 ms
 // at 512^3.)
+// (lines of 384 only: on lines of 512 the double slots' registers spill at 4)
 template <int NYMAX, int NW, bool FULL, bool PERZ, int PH>
-__global__ __launch_bounds__(64 * NW) void k_zpipe_mixed(const cplx<double>* __restrict__ Slo,
+__global__ __launch_bounds__(64 * NW, (zpipe_min_waves<float, NYMAX == 384 ? 384 : 1024, PH>())) void k_zpipe_mixed(const cplx<double>* __restrict__ Slo,
                                                          cplx<float>* __restrict__ S, MidArgs<double> ad,
                                                          MidArgs<float> af, int lo0, int nlo) {
     __shared__ __align__(16) ZpipeLds<float, NYMAX, NW> L;

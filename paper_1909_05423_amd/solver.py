@@ -17,6 +17,7 @@ DTYPES = {"f64": (_lib.PP_F64, torch.float64), "f32": (_lib.PP_F32, torch.float3
           "f32_refined": (_lib.PP_F32_REFINED, torch.float64)}
 GAUGES = {"mean": _lib.PP_GAUGE_MEAN, "pin": _lib.PP_GAUGE_PIN, "pin_raw": _lib.PP_GAUGE_PIN_RAW}
 ZSOLVERS = {"thomas": 0, "pcr": 1, "cr": 2}
+ZSPLITS = {"auto": 0, "off": 1, "on": 2}
 
 
 class Plan:
@@ -24,7 +25,7 @@ class Plan:
     (x-, x+, y-, y+, z-, z+ from 'P', 'D', 'N') and spacings h = (hx, hy, hz)."""
 
     def __init__(self, shape, bc, h, dtype="f64", batch=1, gauge="mean", device=None,
-                 refine_tol=None, refine_max_iter=None, zsolver="thomas"):
+                 refine_tol=None, refine_max_iter=None, zsolver="thomas", zsplit="auto"):
         lib = _lib.load()
         nz, ny, nx = (int(v) for v in shape)
         if dtype not in DTYPES:
@@ -50,6 +51,10 @@ class Plan:
             raise ValueError(f"zsolver must be one of {sorted(ZSOLVERS)}")
         _lib.check(lib.pp_plan_set_zsolver(handle, ZSOLVERS[zsolver]), "pp_plan_set_zsolver")
         self.zsolver = zsolver
+        if zsplit not in ZSPLITS:
+            raise ValueError(f"zsplit must be one of {sorted(ZSPLITS)}")
+        _lib.check(lib.pp_plan_set_zsplit(handle, ZSPLITS[zsplit]), "pp_plan_set_zsplit")
+        self.zsplit = zsplit
         if refine_tol is not None or refine_max_iter is not None:
             _lib.check(lib.pp_plan_set_refinement(handle, 1e-13 if refine_tol is None else float(refine_tol),
                                                   8 if refine_max_iter is None else int(refine_max_iter)),

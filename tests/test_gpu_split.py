@@ -1,0 +1,93 @@
+"""GPU parity of the split Thomas march (section "Solution of the Resulting
+Tridiagonal Matrices": each z-system eliminated from both ends toward a
+meeting point, the two meeting rows solved, then substitution outward), forced
+on through pp_plan_set_zsplit, against the CPU oracle and against the single
+march on the same inputs.
+
+Tolerances (relative max-norm against the oracle) as the other parity tests:
+1e-12 in double and for the refined float solve, 1e-5 for the float solve;
+split and single march agree to the same bounds (they differ only in the
+order of rounding).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32_refined": 1e-12}
+
+
+def _solve(f, bc, h, dtype, zsplit, gauge="mean", batch=1, adjoint=False):
+    import torch
+    from paper_1909_05423_amd import Plan
+    from gpu_util import to_dev
+    plan = Plan(f.shape[-3:], bc, h, dtype=dtype, batch=batch, gauge=gauge, zsplit=zsplit)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    fd = to_dev(f.reshape((batch,) + f.shape[-3:]), tdt)
+    u = plan.adjoint(fd) if adjoint else plan.solve(fd)
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy().reshape(f.shape), plan
+
+
+def _input(rng, shape, dtype):
+    f = rng.standard_normal(shape)
+    return f.astype(np.float32).astype(np.float64) if dtype == "f32" else f
+
+
+# (nz, ny, nx): whole halves (nz a multiple of 16), ragged halves, the
+# shortest split column (two chunks), float lines of 384 (chunks of 6)
+SHAPES = [(32, 12, 16), (37, 9, 6), (16, 8, 8), (61, 24, 27), (48, 384, 4)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32_refined"])
+@pytest.mark.parametrize("bc", ["DDDDDD", "PPPPDN", "NNDDND", "PPNNDD", "DDPPNN"])
+def test_split_vs_oracle_and_single_march(dtype, bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(sum(map(ord, bc + dtype)))
+    for shape in SHAPES:
+        banner(f"split {dtype} {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = _input(rng, shape, dtype)
+        us, _ = _solve(f, bc, h, dtype, "on")
+        u1, _ = _solve(f, bc, h, dtype, "off")
+        uo = oracle.solve(f, bc, h, "mean")
+        assert rel_max(us, uo) < TOL[dtype], (dtype, bc, shape)
+        assert rel_max(us, u1) < TOL[dtype], (dtype, bc, shape)
+
+
+@pytest.mark.parametrize("bc", ["PPPPNN", "NNNNNN", "NNPPNN"])
+@pytest.mark.parametrize("gauge", ["mean", "pin", "pin_raw"])
+@pytest.mark.parametrize("dtype", ["f64", "f32_refined"])
+def test_split_singular_gauges_batch(bc, gauge, dtype):
+    """The pinned zero-mode line (u_0 = 0 in the upper half) and the mean of
+    the zero-mode solution, which the two halves add up, per batch entry."""
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(5)
+    for shape in [(40, 12, 16), (33, 18, 9)]:
+        banner(f"split gauge {dtype} {gauge} {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal((3,) + shape) + np.array([0.3, -1.0, 2.0])[:, None, None, None]
+        us, plan = _solve(f, bc, h, dtype, "on", gauge=gauge, batch=3)
+        _, means, _ = plan.last_info()
+        for b in range(3):
+            uo = oracle.solve(f[b], bc, h, gauge)
+            assert rel_max(us[b], uo) < TOL[dtype], (b, gauge, bc, shape)
+            expect = f[b].mean() if gauge != "pin_raw" else 0.0
+            assert abs(means[b] - expect) < 1e-13 * max(1.0, abs(f[b]).max())
+
+
+def test_split_many_columns_and_adjoint():
+    """512 slots (more workgroups than compute units) and the adjoint solve."""
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(9)
+    shape, bc = (20, 8, 1024), "DDNNDN"
+    h = (1.0 / 1024, 1.0 / 8, 1.0 / 20)
+    f = rng.standard_normal(shape)
+    banner(f"split many columns {shape}")
+    us, _ = _solve(f, bc, h, "f64", "on")
+    assert rel_max(us, oracle.solve(f, bc, h, "mean")) < 1e-12
+    ua, _ = _solve(f, bc, h, "f64", "on", adjoint=True)
+    assert rel_max(ua, oracle.solve_adjoint(f, bc, h, "mean")) < 1e-12

@@ -157,6 +157,24 @@ def test_zsolver_option(lib):
 
 
 
+def test_zsplit_option(lib):
+    st, p = _create(lib, 8, 8, 16, "PPPPDD")
+    assert st == 0
+    for mode in (0, 1, 2, 0):
+        assert lib.pp_plan_set_zsplit(p, mode) == 0
+    assert lib.pp_plan_set_zsplit(p, 3) == -1
+    assert lib.pp_plan_set_zsplit(p, -1) == -1
+    lib.pp_plan_destroy(p)
+    for nx, ny, nz, bc, want in [(8, 8, 16, "PPPPPP", -2),     # periodic z: one march
+                                 (8, 8, 15, "PPPPDD", -3),     # fewer than two chunks of 8 planes
+                                 (8, 2048, 32, "PPPPDD", -3),  # y lines over 1024: the general march
+                                 (8, 384, 12, "PPPPDD", -3)]:  # double lines of 384: chunks of 8
+        st, p = _create(lib, nx, ny, nz, bc)
+        assert st == 0 and lib.pp_plan_set_zsplit(p, 2) == want, (nx, ny, nz, bc)
+        assert lib.pp_plan_set_zsplit(p, 1) == 0 and lib.pp_plan_set_zsplit(p, 0) == 0
+        lib.pp_plan_destroy(p)
+
+
 def test_noalloc_rejects_before_touching_the_gpu(lib):
     """pp_solve_noalloc: argument errors and the fixed-buffer limit are host checks."""
     from paper_1909_05423_amd import _lib
