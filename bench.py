@@ -248,6 +248,7 @@ def main():
     ap.add_argument("--workload", default="div_ppn")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-refined", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true", help="skip timing the plain float solve")
     ap.add_argument("--skip-faces", action="store_true", help="skip timing the solve with face values")
     ap.add_argument("--skip-periodic-z", action="store_true", help="skip timing the periodic-z solve")
     ap.add_argument("--skip-pcr", action="store_true", help="skip timing the PCR and CR-P z solvers")
@@ -412,6 +413,26 @@ def main():
         }
         log(f"f32+refine: {ms_r:.3f} ms/solve, {its} corrections, diff vs f64 {diff:.2e}")
         del plan_r, ur
+
+    if not args.skip_fp32:
+        # the plain float solve (float source, arithmetic and spectra)
+        plan_s = Plan(shape, bc, h, dtype="f32", batch=batch)
+        fs = f.float()
+        us = torch.empty_like(fs)
+        ms_s, _, per_s = time_solves(plan_s, fs, us, args.steps, args.warmup, lib)
+        ab32 = algorithmic_bytes(shape, batch, slots, 4, 8)
+        kern_s = {g: dict(per_s[g]) for g in GROUPS}
+        for g in ab32:
+            if per_s[g]["avg_ms"]:
+                kern_s[g]["algorithmic_GBs"] = round(ab32[g] / (per_s[g]["avg_ms"] * 1e-3) / 1e9, 1)
+        result["fp32"] = {
+            "value": round(npts / ms_s / 1e3, 1), "unit": "Mpts/s", "ms_per_step": round(ms_s, 4),
+            "max_rel_diff_vs_f64": float((us.double() - u).abs().max() / u.abs().max()),
+            "solve_hbm_GBs": round(sum(ab32.values()) / (ms_s * 1e-3) / 1e9, 1),
+            "kernels": kern_s,
+        }
+        log(f"f32: {ms_s:.3f} ms/solve")
+        del plan_s, fs, us
 
     if not args.skip_cpu_baseline:
         log("timing the oracle on a slab of the full grid")

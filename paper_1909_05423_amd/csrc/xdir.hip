@@ -107,16 +107,17 @@ template <typename T> __device__ __forceinline__ void put_spec(cplx<T>* p, const
 // around a memory instruction, so that count is exact; the first block is
 // issued outside the loop so every pass through it sees the same sequence.
 // Minimum waves per SIMD the compiler must leave room for.  2 for the
-// all-float forward kernel (on rows of 1024 it would otherwise take every
-// register and run one wave per SIMD; measured 1.64 -> 1.21 ms at
-// 1024 x 1024 x 512) and for the double kernel on rows of 512 without face
-// values (4 registers over the budget of two waves); no constraint elsewhere
-// (the other kernels with double data spill under it).
-// The general form of the fused residual (RES) keeps no such constraint: it
-// spills under it.
+// all-float forward kernel on rows up to 512 and for the double kernel on
+// rows of 512 without face values (4 registers over the budget of two waves);
+// no constraint elsewhere: the kernels with double data, and the float kernel
+// on rows of 1024, spill under it (the float one 104 registers, 3.0 ms at
+// 1024 x 1024 x 512; unconstrained it takes AGPRs instead, one wave per SIMD,
+// 1.75 ms).  The general form of the fused residual (RES) spills under it too.
 template <typename T, typename Tin, int RMAX, bool FACES, bool FULL = true, bool RES = false>
 constexpr int kXfwdMinWaves =
-    (RES && !FULL) ? 1 : ((sizeof(T) == 4 && sizeof(Tin) == 4) || (sizeof(T) == 8 && RMAX == 8 && !FACES)) ? 2 : 1;
+    (RES && !FULL) ? 1
+                   : ((sizeof(T) == 4 && sizeof(Tin) == 4 && RMAX <= 8) || (sizeof(T) == 8 && RMAX == 8 && !FACES)) ? 2
+                                                                                                                     : 1;
 
 // RES: the fused refinement residual (XArgs::u0 ...): besides the source
 // rows, each lane fetches its own u0 values of the two rows, of the rows
