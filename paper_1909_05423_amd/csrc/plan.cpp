@@ -1113,7 +1113,8 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     int lines;
     {
         const int epl = (nx + 63) / 64;
-        const int lpw = std::max(1, pp::xdir_rmax(nx) / epl);
+        // (rows of 256: one line per wavefront, the exact-count form with four values per lane)
+        const int lpw = (nx == 256) ? 1 : std::max(1, pp::xdir_rmax(nx) / epl);
         lines = std::min(pp::kXWaves * lpw, (ny + 1) / 2);
         // the inverse gathers slots * lines (slot, row pair) values, rmax/2 per thread
         while (lines > 1 && (size_t)((nx + 1) / 2) * lines > (size_t)pp::kXThreads * (pp::xdir_rmax(nx) / 2)) --lines;

@@ -859,9 +859,11 @@ hipError_t launch_xfwd_res(const double* f, cplx<float>* S, double* partial, con
     if (a.nx > 512) return hipErrorInvalidValue;
     const FaceArgs<double> none{};
     if (faces) {
+        if (a.nx == 256) return launch_xfwd_shape<double, double, float, 4, true, true>(f, S, partial, a, batch, *faces, s);
         if (a.nx == 384) return launch_xfwd_shape<double, double, float, 6, true, true>(f, S, partial, a, batch, *faces, s);
         return launch_xfwd_shape<double, double, float, 8, true, true>(f, S, partial, a, batch, *faces, s);
     }
+    if (a.nx == 256) return launch_xfwd_shape<double, double, float, 4, false, true>(f, S, partial, a, batch, none, s);
     if (a.nx == 384) return launch_xfwd_shape<double, double, float, 6, false, true>(f, S, partial, a, batch, none, s);
     return launch_xfwd_shape<double, double, float, 8, false, true>(f, S, partial, a, batch, none, s);
 }
@@ -869,7 +871,9 @@ hipError_t launch_xfwd_res(const double* f, cplx<float>* S, double* partial, con
 template <typename T, typename Tin, typename Ts, bool FACES>
 static hipError_t launch_xfwd_any(const Tin* f, cplx<Ts>* S, double* partial, const XArgs<T>& a, int batch,
                                   const FaceArgs<Tin>& fa, hipStream_t s) {
-    // rows of 384 = 64 x 6: exact-count form with six values per lane
+    // rows of 256 = 64 x 4 and 384 = 64 x 6: exact-count forms with four and
+    // six values per lane
+    if (a.nx == 256) return launch_xfwd_shape<T, Tin, Ts, 4, FACES>(f, S, partial, a, batch, fa, s);
     if (a.nx == 384) return launch_xfwd_shape<T, Tin, Ts, 6, FACES>(f, S, partial, a, batch, fa, s);
     if (a.nx <= 512) return launch_xfwd_shape<T, Tin, Ts, 8, FACES>(f, S, partial, a, batch, fa, s);
     if (a.nx <= 1024) return launch_xfwd_shape<T, Tin, Ts, 16, FACES>(f, S, partial, a, batch, fa, s);
@@ -911,6 +915,8 @@ template <typename T, typename Tout, typename Tp, int MODE>
 static hipError_t launch_xinv_any(const cplx<T>* S, Tout* u, const Tp* uprev, const XArgs<T>& a, int batch,
                                   const double* shift, const double* scalars, int gauge_region, double* partial,
                                   hipStream_t s) {
+    if (a.nx == 256)   // 64 x 4: exact-count form with four values per lane
+        return launch_xinv_shape<T, Tout, Tp, MODE, 4>(S, u, uprev, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx == 384)   // 64 x 6: exact-count form with six values per lane
         return launch_xinv_shape<T, Tout, Tp, MODE, 6>(S, u, uprev, a, batch, shift, scalars, gauge_region, partial, s);
     if (a.nx <= 512)

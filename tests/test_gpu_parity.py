@@ -116,7 +116,8 @@ def test_refined_matches_oracle(bc):
 # residual for rows of 1024), general forms, faces, batches, both gauges.
 ONE_CORRECTION = [((8, 8, 512), "PPPPNN", False), ((8, 16, 1024), "PPPPNN", True), ((16, 512, 16), "PPPPNN", True),
                   ((16, 512, 512), "PPPPNN", True), ((8, 8, 512), "DDNNDN", True), ((12, 384, 384), "DDDDDD", False),
-                  ((9, 24, 36), "NNPPNN", True), ((7, 12, 1024), "DDNNNN", False), ((24, 48, 18), "PPPPPP", False)]
+                  ((9, 24, 36), "NNPPNN", True), ((7, 12, 1024), "DDNNNN", False), ((24, 48, 18), "PPPPPP", False),
+                  ((12, 16, 256), "DDNNNN", False)]
 
 
 @pytest.mark.parametrize("case", ONE_CORRECTION, ids=lambda c: f"{c[1]}-{c[0]}-{'faces' if c[2] else 'nofaces'}")
@@ -162,7 +163,7 @@ def test_batched_equals_single():
 
 # batch entries through the exact-count kernel forms (x rows of 384 / 512 /
 # 1024, y lines of 384 / 512 / 1024)
-BATCH_FULL_SHAPES = [(8, 16, 512), (8, 512, 16), (8, 8, 1024), (8, 1024, 4), (12, 16, 384), (12, 384, 8)]
+BATCH_FULL_SHAPES = [(8, 16, 512), (8, 512, 16), (8, 8, 1024), (8, 1024, 4), (12, 16, 384), (12, 384, 8), (8, 16, 256)]
 
 
 @pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDD"])
@@ -235,9 +236,10 @@ def test_mms_ppd_workload_small():
     assert rel_max(u, uo) < 1e-12
 
 
-# Shapes that take the exact-count (FULL) kernel forms: x lines of 64 * 8 and
-# 64 * 16 in blocks of 8 rows, y lines of 512 in chunks of 8 planes; and one
-# ragged neighbour of each that takes the general form of the same kernel.
+# Shapes that take the exact-count (FULL) kernel forms: x lines of 64 * 4,
+# 64 * 6, 64 * 8 and 64 * 16 in blocks of 8 rows, y lines of 384 and 512 in
+# whole chunks; and ragged neighbours that take the general form of the same
+# kernel.
 # These long lines use the unit-cube spacing h = 1/n of the paper's problems:
 # with spacings drawn at random, a line of 512 or more cells can be so much
 # longer than the others that the exact solution is ill-conditioned enough for
@@ -245,7 +247,7 @@ def test_mms_ppd_workload_small():
 # number) to exceed 1e-12; on the unit cube it stays below 1e-13 for every
 # shape and boundary set here (checked with a long-double residual correction).
 FULL_SHAPES = [(8, 8, 512), (16, 512, 16), (8, 16, 1024), (16, 512, 512), (9, 8, 512), (13, 512, 12), (8, 12, 512),
-               (8, 16, 384), (6, 12, 384), (12, 384, 8), (7, 384, 6)]
+               (8, 16, 384), (6, 12, 384), (12, 384, 8), (7, 384, 6), (8, 16, 256), (5, 12, 256), (3, 8, 256)]
 
 
 @pytest.mark.parametrize("bc", ["PPPPNN", "DDNNDD", "NNDDND", "PPPPDD"])
