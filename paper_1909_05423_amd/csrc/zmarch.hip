@@ -521,9 +521,12 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     cplx<T> st[OWN];
 #pragma unroll
     for (int o = 0; o < OWN; ++o) st[o] = mk<T>(T(0), T(0));
+    // the split march's float halves load each chunk's pivots just before its
+    // recurrences (registers: their prefetch would be live across the transforms)
+    constexpr bool LATEPIV = PH != 0 && sizeof(Tf) == 4 && sizeof(T) == 4;
     if constexpr (PH != 2) {
         load_plane(0);
-        load_piv(0);
+        if constexpr (!LATEPIV) load_piv(0);
     }
     auto up_chunk = [&](int c) __attribute__((always_inline)) {
         const int zc = c * kSZ;
@@ -605,6 +608,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
         }
         lds_barrier();
         }
+        if constexpr (LATEPIV) load_piv(zc);
         // forward elimination over the chunk; eliminated right-hand sides go to HBM
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
@@ -640,7 +644,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
             }
             st[o] = prev;
         }
-        load_piv(min(zc + kSZ, last));   // the last chunk reloads its own pivots for the way down
+        if constexpr (!LATEPIV) load_piv(min(zc + kSZ, last));   // the last chunk reloads its own pivots for the way down
     };
     // the first chunk is issued outside the loop so that every pass through the
     // loop sees the same sequence of memory operations before it
@@ -660,7 +664,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     // ----------------------------------------------------------- downward
     // the top chunk's eliminated right-hand sides were stored by this thread
     // (same entries, same addresses): read them back in program order
-    if constexpr (PH == 2) load_piv(last);
+    if constexpr (PH == 2 && !LATEPIV) load_piv(last);
     load_entry(last);
 #pragma unroll
     for (int o = 0; o < OWN; ++o) {
@@ -689,6 +693,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
         const int zc = c * kSZ;
         const int nl = FULL ? kSZ : min(kSZ, nz - zc);
         lds_barrier();   // the previous inverse transforms are done with the work buffer
+        if constexpr (LATEPIV) load_piv(zc);
         // back substitution over the chunk, from registers into the work buffer
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
@@ -729,7 +734,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
         lds_barrier();
         const int zn = zc >= kSZ ? zc - kSZ : 0;
         load_entry(zn);
-        load_piv(zn);
+        if constexpr (!LATEPIV) load_piv(zn);
         // inverse y transform of this wave's plane, written straight to HBM
         if (FULL || wave < nl) {
             cplx<Tf>* line = work + wave * LDY;
