@@ -211,6 +211,10 @@ hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s)
 
 // Compute units of the current device (256 if the query fails).
 int device_cus();
+// Raise a kernel's dynamic-LDS limit to `bytes` on the current device, once
+// per (kernel, device) and thread-safe; returns the error of the attribute
+// call (hipSuccess when already set).
+hipError_t allow_dynamic_lds(const void* kernel, int bytes);
 // Planes per chunk of the pipelined z march for lines of ny in double or float
 // (0: no pipelined form, ny over 1024); the split march puts its meeting
 // point on a multiple of it.

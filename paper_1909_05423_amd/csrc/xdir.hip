@@ -23,6 +23,9 @@
 // Writing columns with y contiguous is the x <-> y transpose, done through LDS
 // so that both the row reads and the column writes are coalesced.
 
+#include <mutex>
+#include <set>
+#include <tuple>
 #include <type_traits>
 
 #include "pp_kernels.hpp"
@@ -795,15 +798,23 @@ template <typename T> static size_t x_lds_bytes(const XArgs<T>& a) {
     return ((size_t)(a.ty >> 1) * a.ldl + 2 * (size_t)a.nx) * sizeof(cplx<T>);
 }
 
-// Allow the kernel the dynamic LDS it may ask for (lines + twiddle tables);
-// once per kernel (the template argument is the kernel itself).
-template <auto K> static void allow_lds() {
-    static bool done = false;
-    if (!done) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kXLdsMax);
-        done = true;
-    }
+hipError_t allow_dynamic_lds(const void* kernel, int bytes) {
+    static std::mutex mu;
+    static std::set<std::tuple<const void*, int, int>> done;   // (kernel, device, bytes)
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({kernel, dev, bytes})) return hipSuccess;
+    const hipError_t r = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (r == hipSuccess) done.insert({kernel, dev, bytes});
+    return r;
+}
+
+// Allow the kernel the dynamic LDS it may ask for (lines + twiddle tables)
+// (the template argument is the kernel itself).
+template <auto K> static hipError_t allow_lds() {
+    return allow_dynamic_lds(reinterpret_cast<const void*>(K), kXLdsMax);
 }
 
 int device_cus() {
@@ -837,7 +848,8 @@ static hipError_t launch_xfwd_shape(const Tin* f, cplx<Ts>* S, double* partial, 
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
     if constexpr (RMAX <= 16) {
         if (x_full<RMAX>(a)) {
-            allow_lds<k_xfwd<T, Tin, Ts, kXThreads, RMAX, true, FACES, RES>>();
+            const hipError_t le = allow_lds<k_xfwd<T, Tin, Ts, kXThreads, RMAX, true, FACES, RES>>();
+            if (le != hipSuccess) return le;
             hipLaunchKernelGGL((k_xfwd<T, Tin, Ts, kXThreads, RMAX, true, FACES, RES>),
                                dim3(x_launch_grid(nb, false)), dim3(kXThreads), x_lds_bytes(a), s, f, S, partial, a,
                                nb, fa);
@@ -845,7 +857,8 @@ static hipError_t launch_xfwd_shape(const Tin* f, cplx<Ts>* S, double* partial, 
         }
     }
     {
-        allow_lds<k_xfwd<T, Tin, Ts, kXThreads, RMAX, false, FACES, RES>>();
+        const hipError_t le = allow_lds<k_xfwd<T, Tin, Ts, kXThreads, RMAX, false, FACES, RES>>();
+        if (le != hipSuccess) return le;
         hipLaunchKernelGGL((k_xfwd<T, Tin, Ts, kXThreads, RMAX, false, FACES, RES>), dim3(x_launch_grid(nb, false)),
                            dim3(kXThreads), x_lds_bytes(a), s, f, S, partial, a, nb, fa);
     }
@@ -895,7 +908,8 @@ static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const Tp* uprev, 
     const int nb = x_blocks(a.ny, a.ty, a.nz, batch);
     if constexpr (RMAX <= 16) {
         if (x_full<RMAX>(a)) {
-            allow_lds<k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, true>>();
+            const hipError_t le = allow_lds<k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, true>>();
+            if (le != hipSuccess) return le;
             hipLaunchKernelGGL((k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, true>),
                                dim3(x_launch_grid(nb, sizeof(T) == 4)), dim3(kXThreads), x_lds_bytes(a), s, S, u,
                                uprev, a, shift, scalars, gauge_region, partial, nb);
@@ -903,7 +917,8 @@ static hipError_t launch_xinv_shape(const cplx<T>* S, Tout* u, const Tp* uprev, 
         }
     }
     {
-        allow_lds<k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, false>>();
+        const hipError_t le = allow_lds<k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, false>>();
+        if (le != hipSuccess) return le;
         hipLaunchKernelGGL((k_xinv<T, Tout, Tp, kXThreads, MODE, RMAX, false>),
                            dim3(x_launch_grid(nb, sizeof(T) == 4)), dim3(kXThreads), x_lds_bytes(a), s, S, u, uprev,
                            a, shift, scalars, gauge_region, partial, nb);

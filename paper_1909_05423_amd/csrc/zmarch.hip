@@ -933,12 +933,8 @@ static hipError_t launch_pipe_any(cplx<T>* S, const MidArgs<T>& a, int batch, hi
 template <typename T, int RMAX, int OWN>
 static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     const size_t lds = zmarch_lds_bytes(a.zb, a.ldy, a.ny, sizeof(cplx<T>));
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zmarch<T, kZThreads, RMAX, OWN>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kZLdsBytes);
-        attr = true;
-    }
+    const hipError_t le = allow_dynamic_lds(reinterpret_cast<const void*>(k_zmarch<T, kZThreads, RMAX, OWN>), kZLdsBytes);
+    if (le != hipSuccess) return le;
     hipLaunchKernelGGL((k_zmarch<T, kZThreads, RMAX, OWN>), dim3(a.slots, batch), dim3(kZThreads), lds, s, S, a);
     return hipGetLastError();
 }

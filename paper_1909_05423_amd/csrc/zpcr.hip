@@ -579,22 +579,20 @@ __global__ __launch_bounds__(kPcrThreads) void k_zcr2(cplx<Tio>* __restrict__ S,
 template <typename T>
 hipError_t launch_mid_pcr(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s, bool cr) {
     if (a.nz > kPcrRowsMax || a.ny > 512) return hipErrorInvalidValue;
-    const dim3 gy(a.slots, (a.nz + 7) / 8, batch);
-    hipLaunchKernelGGL((k_ypass<T, false>), gy, dim3(512), 0, s, S, a);
-    static bool attr = false;   // once per process: the largest tile any plan asks for
-    if (!attr) {
+    {
+        // the largest tile any plan asks for, once per kernel and device
         const int maxb = (int)((size_t)kPcrRowsMax * 3 * sizeof(double) + 64 * sizeof(double));
         const int maxb2 = (int)((size_t)kPcrPairRows * (sizeof(double2) + 4 * sizeof(double)) + 64 * sizeof(double));
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zpcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  maxb);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zcr<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  maxb);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zpcr2<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, maxb2);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_zcr2<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, maxb2);
-        attr = true;
+        const void* k1[2] = {reinterpret_cast<const void*>(k_zpcr<T>), reinterpret_cast<const void*>(k_zcr<T>)};
+        const void* k2[2] = {reinterpret_cast<const void*>(k_zpcr2<T>), reinterpret_cast<const void*>(k_zcr2<T>)};
+        for (int i = 0; i < 2; ++i) {
+            hipError_t le = allow_dynamic_lds(k1[i], maxb);
+            if (le == hipSuccess) le = allow_dynamic_lds(k2[i], maxb2);
+            if (le != hipSuccess) return le;
+        }
     }
+    const dim3 gy(a.slots, (a.nz + 7) / 8, batch);
+    hipLaunchKernelGGL((k_ypass<T, false>), gy, dim3(512), 0, s, S, a);
     const int te = pcr_entries(a.nz);
     if (te > 0) {
         const dim3 gz((a.ny + te - 1) / te, a.slots, batch);
