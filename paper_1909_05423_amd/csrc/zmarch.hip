@@ -334,9 +334,15 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 // The order of issue is chosen so that, with in-order completion of vector
 // memory operations, every wait retires only what it needs: at each point of
 // use, the operations issued after the awaited load are a fixed set (one
-// chunk's stores, or one chunk's prefetch).  FULL (ny == NYMAX, nz a multiple
-// of NW) removes every data-dependent branch around memory instructions, so the
-// compiler can count them exactly; barriers order LDS only.
+// chunk's stores, or one chunk's prefetch).  FULL (ny == NYMAX, the rows of
+// the march a multiple of NW) removes every data-dependent branch around
+// memory instructions, so the compiler can count them exactly; barriers order
+// LDS only.  (The float halves of the split march load each chunk's pivots
+// right before its recurrences instead: see LATEPIV.)
+//
+// Where the columns are few, the march of a column is split between two
+// workgroups (PH 1 and 2 of zpipe_body, two launches): both halves eliminate
+// toward a meeting point near the middle of z, then substitute away from it.
 //
 // The march itself is zpipe_body, which works in precision T on a column it
 // reads (upward) from `icol` in precision Tin and writes (eliminated right-hand
