@@ -149,9 +149,9 @@ pp_status pp_plan_set_zsplit(pp_plan p, pp_zsplit mode);
  * the ratio of the last two corrections, or, after the first, times the first
  * correction itself (the float solve's relative error, which the correction's
  * solve is taken to repeat).  The float solves transform along x in double and
- * keep the spectra of the 16 lowest x-wavenumber slots in double (rows and y
- * lines up to 512 in the z march; otherwise those slots run in float too and
- * more corrections may be needed). */
+ * keep the spectra of the 16 lowest x-wavenumber slots in double through the
+ * z march (y lines up to 1024; on longer lines those slots run in float too
+ * and more corrections may be needed). */
 pp_status pp_plan_set_refinement(pp_plan p, double tol, int max_iter);
 
 /* Bytes of device workspace the caller must pass to pp_solve/pp_solve_adjoint

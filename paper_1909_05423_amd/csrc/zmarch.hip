@@ -984,7 +984,7 @@ static hipError_t launch_mixed(const cplx<double>* Slo, cplx<float>* S, const Mi
     return hipGetLastError();
 }
 
-bool mixed_march_supported(int ny, int zsolver) { return zsolver == 0 && ny <= 512; }
+bool mixed_march_supported(int ny, int zsolver) { return zsolver == 0 && ny <= 1024; }
 
 hipError_t launch_mid_mixed(const cplx<double>* Slo, cplx<float>* S, const MidArgs<double>& ad,
                             const MidArgs<float>& af, int lo0, int nlo, int batch, hipStream_t s) {
@@ -993,14 +993,25 @@ hipError_t launch_mid_mixed(const cplx<double>* Slo, cplx<float>* S, const MidAr
         const size_t lds = (2 * (size_t)af.ny + (size_t)kYpreWaves * af.ldy) * sizeof(cplx<double>);
         cplx<double>* lo = const_cast<cplx<double>*>(Slo);
         const int grid = (nplanes + kYpreWaves - 1) / kYpreWaves;
-        if (af.ny <= 384) hipLaunchKernelGGL(k_ypre<6>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
-        else hipLaunchKernelGGL(k_ypre<8>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
+        if (af.ny <= 384) {
+            hipLaunchKernelGGL(k_ypre<6>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
+        } else if (af.ny <= 512) {
+            hipLaunchKernelGGL(k_ypre<8>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
+        } else {
+            const hipError_t le = allow_dynamic_lds(reinterpret_cast<const void*>(k_ypre<16>), (int)lds);
+            if (le != hipSuccess) return le;
+            hipLaunchKernelGGL(k_ypre<16>, dim3(grid), dim3(64 * kYpreWaves), lds, s, lo, ad, lo0, nlo, nplanes);
+        }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (af.ny == 384) {
         if (pipe_full(af, 384, 6)) return launch_mixed<384, 6, true>(Slo, S, ad, af, lo0, nlo, batch, s);
         return launch_mixed<384, 6, false>(Slo, S, ad, af, lo0, nlo, batch, s);
+    }
+    if (af.ny > 512) {
+        if (pipe_full(af, 1024, 8)) return launch_mixed<1024, 8, true>(Slo, S, ad, af, lo0, nlo, batch, s);
+        return launch_mixed<1024, 8, false>(Slo, S, ad, af, lo0, nlo, batch, s);
     }
     if (pipe_full(af, 512, 8)) return launch_mixed<512, 8, true>(Slo, S, ad, af, lo0, nlo, batch, s);
     return launch_mixed<512, 8, false>(Slo, S, ad, af, lo0, nlo, batch, s);
