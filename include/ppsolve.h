@@ -137,8 +137,9 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
  * The split form exists for non-periodic z, y lines up to 1024 and nz of at
  * least two chunks of the march (16 planes; 12 for float lines of 384, 8 for
  * double lines over 512): PP_ZSPLIT_ON on other shapes returns PP_ERR_BC
- * (periodic z) or PP_ERR_SIZE.  Both layouts compute the same elimination up
- * to the order of its rounding. */
+ * (periodic z) or PP_ERR_SIZE.  Both layouts solve the same z-systems (the
+ * lower half with the pivots of the reversed system); their results differ
+ * by rounding only. */
 typedef enum { PP_ZSPLIT_AUTO = 0, PP_ZSPLIT_OFF = 1, PP_ZSPLIT_ON = 2 } pp_zsplit;
 pp_status pp_plan_set_zsplit(pp_plan p, pp_zsplit mode);
 
