@@ -180,8 +180,9 @@ def device_copy_bandwidth(lib, reps=10):
 def zsolver_sweep(lib, warmup, steps=10, bc="PPPPNN"):
     """The paper's comparison of the tridiagonal solvers (section "Comparison of
     Tridiagonal Solvers"): 64 x 64 x nz grids, nz = 2^n - 1 up to 4095, the
-    whole f64 solve timed with the fused Thomas march, PCR and CR-P (the last
-    two with the y transforms as separate passes).  Seeded N(0,1) source."""
+    whole f64 solve timed with the fused Thomas march (its automatic layout,
+    and forced segmented), PCR and CR-P (the last two with the y transforms
+    as separate passes).  Seeded N(0,1) source."""
     import numpy as np
     import torch
     from paper_1909_05423_amd import Plan
@@ -193,8 +194,11 @@ def zsolver_sweep(lib, warmup, steps=10, bc="PPPPNN"):
         u = torch.empty_like(f)
         row = {"nz": nz}
         ref = None
-        for key in ("thomas", "pcr", "cr"):
-            plan = Plan(shape, bc, h, dtype="f64", zsolver=key)
+        for key in ("thomas", "thomas_segmented", "pcr", "cr"):
+            if key == "thomas_segmented":   # forced: the automatic choice keeps the zero mode's column whole
+                plan = Plan(shape, bc, h, dtype="f64", zsplit="seg")
+            else:
+                plan = Plan(shape, bc, h, dtype="f64", zsolver=key)
             ms, _, _ = time_solves(plan, f, u, steps, warmup, lib)
             row[f"{key}_ms"] = round(ms, 4)
             if ref is None:
@@ -203,8 +207,8 @@ def zsolver_sweep(lib, warmup, steps=10, bc="PPPPNN"):
                 row[f"{key}_max_rel_diff_vs_thomas"] = float((u - ref).abs().max() / ref.abs().max())
             del plan
         rows.append(row)
-        log(f"64 x 64 x {nz}: Thomas {row['thomas_ms']:.3f} ms, PCR {row['pcr_ms']:.3f} ms, "
-            f"CR-P {row['cr_ms']:.3f} ms")
+        log(f"64 x 64 x {nz}: Thomas {row['thomas_ms']:.3f} ms (segmented {row['thomas_segmented_ms']:.3f} ms), "
+            f"PCR {row['pcr_ms']:.3f} ms, CR-P {row['cr_ms']:.3f} ms")
         del f, u, ref
     return {"shape": "64 x 64 x nz", "bc": bc, "dtype": "f64", "rows": rows}
 

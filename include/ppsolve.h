@@ -131,16 +131,29 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
 /* Layout of the Thomas march (PP_ZSOLVER_THOMAS; the other solvers ignore it).
  *   PP_ZSPLIT_AUTO  default: split where the columns (x-wavenumber slots times
  *                   batch) are at most 1/2 (PP_F64), 2 (PP_F32) or 4
- *                   (PP_F32_REFINED) per compute unit of the device;
+ *                   (PP_F32_REFINED) per compute unit of the device, and
+ *                   segmented where the plan has segments (below), provided
+ *                   no z-system is so close to singular that splitting it
+ *                   amplifies rounding by more than 256 (the zero mode and
+ *                   lowest wavenumbers of long columns under Neumann or
+ *                   periodic x, y faces: about nz / 2 for the zero mode);
  *   PP_ZSPLIT_OFF   always one workgroup per column;
- *   PP_ZSPLIT_ON    always split (two workgroups per column).
+ *   PP_ZSPLIT_ON    always split in two (two workgroups per column);
+ *   PP_ZSPLIT_SEG   always segmented: each column in 3 to 16 segments (enough
+ *                   for about 256 workgroups), each eliminated on its own,
+ *                   their end rows coupled through a small reduced system
+ *                   solved between two launches (f64 and f32 plans whose
+ *                   columns number at most 85 and whose nz holds three
+ *                   segments of at least two chunks).
  * The split form exists for non-periodic z, y lines up to 1024 and nz of at
  * least two chunks of the march (16 planes; 12 for float lines of 384, 8 for
- * double lines over 512): PP_ZSPLIT_ON on other shapes returns PP_ERR_BC
- * (periodic z) or PP_ERR_SIZE.  Both layouts solve the same z-systems (the
- * lower half with the pivots of the reversed system); their results differ
- * by rounding only. */
-typedef enum { PP_ZSPLIT_AUTO = 0, PP_ZSPLIT_OFF = 1, PP_ZSPLIT_ON = 2 } pp_zsplit;
+ * double lines over 512): PP_ZSPLIT_ON / PP_ZSPLIT_SEG on other shapes return
+ * PP_ERR_BC (periodic z) or PP_ERR_SIZE.  All layouts solve the same
+ * z-systems; forced splits of near-singular systems carry errors up to about
+ * the amplification above times the unit roundoff (measured: 1.3e-12
+ * relative for the two-way split and 3e-12 segmented at 16 x 16 x 1023 with
+ * Neumann z and periodic x, y, against 3.5e-15 for one march). */
+typedef enum { PP_ZSPLIT_AUTO = 0, PP_ZSPLIT_OFF = 1, PP_ZSPLIT_ON = 2, PP_ZSPLIT_SEG = 3 } pp_zsplit;
 pp_status pp_plan_set_zsplit(pp_plan p, pp_zsplit mode);
 
 /* Refinement controls for PP_F32_REFINED: stop once the estimated relative

@@ -35,6 +35,11 @@ struct Tables {
     size_t t_bmid = 0;   // interior z diagonal per (slot, entry, part)
     // split march: the lower half's pivots (by distance from the bottom row) and the meeting rows
     size_t t_browoff = 0, t_belen = 0, t_bwinf = 0, t_bwrows = 0, t_meet = 0;
+    // segmented march: fresh pivots of a segment starting inside the column,
+    // its forward-eliminated first unit vector (rho), the last segment's
+    // last-row values, and the end values of the segments' responses
+    size_t t_frowoff = 0, t_felen = 0, t_fwinf = 0, t_fwrows = 0, t_flast = 0;
+    size_t t_rrowoff = 0, t_relen = 0, t_rrows = 0, t_rholast = 0, t_segk = 0;
     // periodic z (Sherman-Morrison)
     size_t t_aelen = 0, t_qelen = 0;
     size_t t_aoff = 0, t_alen = 0, t_arows = 0, t_qoff = 0, t_qlen = 0, t_qrows = 0, t_qlast = 0, t_invden = 0,
@@ -69,6 +74,14 @@ struct pp_plan_s {
     // Used when the columns alone would leave compute units idle.
     int zsplit = 0;
     int zsplit_mode = 0;   // pp_zsplit
+    // segmented march (few columns, long z): zsegs segments of zseglen rows
+    // (the last one the remainder); 0 if the plan has no segmented form
+    int zsegs = 0, zseglen = 0;
+    // largest 1 / |1 - v w| of the split march's meeting rows (the factor by
+    // which they amplify rounding): near-singular z-systems (the zero mode,
+    // the lowest wavenumbers of long columns with Neumann or periodic x, y)
+    // make it large, and the automatic choice then keeps one march per column
+    double split_gmax = 0.0;
     // refined solve: slots lo0 .. lo0+nlo-1 kept in double by the x transform and the z march
     int lo0 = 0, nlo = 0;
     // the first correction's size may stand for the refinement's contraction
@@ -79,6 +92,7 @@ struct pp_plan_s {
     // o_lo the double slots
     size_t o_scalars = 0, o_partial = 0, o_tab[2] = {0, 0}, o_S = 0, o_r = 0, o_u0 = 0, o_lo = 0, ws_bytes = 0;
     size_t o_zb[2] = {0, 0};   // split march: the halves' last eliminated values, per table set
+    size_t o_seg = 0;          // segmented march: segment end values, reduction scratch, couplings
     unsigned long long serial = 0;   // identifies the plan in the workspace registry
     // last call
     void* last_ws = nullptr;
@@ -100,6 +114,13 @@ struct pp_plan_s {
 namespace {
 
 constexpr size_t kAlign = 256;
+// segmented march: at most this many segments per column, and segments enough
+// for this many workgroups (the compute units of an MI355X)
+constexpr int kMaxSegments = 16;
+constexpr long long kSegTargetColumns = 256;
+// the automatic choice splits columns only where the meeting rows amplify
+// rounding by at most this much (measured: errors near 2.5e-15 times it)
+constexpr double kSplitGMax = 256.0;
 
 // Which plan's tables each workspace holds: workspace base pointer -> serial
 // number of the plan that last uploaded its tables there.  A solve re-uploads
@@ -346,6 +367,80 @@ template <typename T> void bottom_pivots(double lam, int nz, double hz, int bz1,
     for (int i = 0; i < L; ++i) out->body[i] = (T)seq[i];
 }
 
+// Segmented march (section "Solution of the Resulting Tridiagonal Matrices",
+// the Thomas algorithm run on pieces of each z-system): segment s of nseg
+// holds rows [s L, s L + len_s) and is eliminated on its own ("fresh": the
+// coupling to the rows outside is moved to the right-hand side), with the
+// global top pivots in segment 0 and the pivots of a segment that starts with
+// the interior diagonal elsewhere (the last segment's last row with the bottom
+// face).  Per line: those fresh pivots (stored up to convergence), rho =
+// the fresh elimination of the segment's first unit vector (the effect of the
+// coupling above it; stored until negligible), the last segment's last-row
+// pivot and rho, and for the first, interior and last segment the first and
+// last values of p = T_s^{-1} e_first and q = T_s^{-1} e_last, which link the
+// segments' end values in the reduced system.
+template <typename T> struct SegLine {
+    std::vector<T> fbody, rho;
+    T finf = 0, flast = 0, rholast = 0;
+    int ftail = 0;
+    double k[3][4] = {{0}};   // class (first, interior, last) x (p_first, p_last, q_first, q_last)
+};
+
+static void seg_ends(const std::vector<double>& piv, double* k) {
+    const int L = (int)piv.size();
+    std::vector<double> rho(L), pv(L), qv(L);
+    for (int j = 0; j < L; ++j) rho[j] = (j == 0) ? piv[0] : -piv[j] * rho[j - 1];
+    pv[L - 1] = rho[L - 1];
+    for (int j = L - 2; j >= 0; --j) pv[j] = rho[j] - piv[j] * pv[j + 1];
+    qv[L - 1] = piv[L - 1];
+    for (int j = L - 2; j >= 0; --j) qv[j] = -piv[j] * qv[j + 1];
+    k[0] = pv[0];
+    k[1] = pv[L - 1];
+    k[2] = qv[0];
+    k[3] = qv[L - 1];
+}
+
+template <typename T>
+void seg_line(double lam, int nz, double hz, int bz0, int bz1, bool pinned, int L, int nseg, SegLine<T>* out) {
+    const double bmid = -2.0 + hz * hz * lam;
+    const double d0 = (bz0 == pp::BC_D) ? -1.0 : 1.0;
+    const double d1 = (bz1 == pp::BC_D) ? -1.0 : 1.0;
+    const int Llast = nz - (nseg - 1) * L;
+    // first segment: the global top pivots
+    std::vector<double> pf(L);
+    pf[0] = pinned ? 0.0 : 1.0 / (bmid + d0);
+    for (int j = 1; j < L; ++j) pf[j] = 1.0 / (bmid - pf[j - 1]);
+    seg_ends(pf, out->k[0]);
+    // interior segments: fresh pivots from the interior diagonal
+    std::vector<double> fi(L);
+    fi[0] = 1.0 / bmid;
+    for (int j = 1; j < L; ++j) fi[j] = 1.0 / (bmid - fi[j - 1]);
+    seg_ends(fi, out->k[1]);
+    // last segment: the same, its last row with the bottom face
+    std::vector<double> fl(fi.begin(), fi.begin() + Llast);
+    fl[Llast - 1] = 1.0 / ((bmid + d1) - (Llast > 1 ? fi[Llast - 2] : 0.0));
+    seg_ends(fl, out->k[2]);
+    out->flast = (T)fl[Llast - 1];
+    // stored fresh pivots: up to the value at L - 1 (rows past the tail read finf)
+    out->finf = (T)fi[L - 1];
+    int tail = L;
+    while (tail > 0 && (T)fi[tail - 1] == out->finf) --tail;
+    out->ftail = tail;
+    out->fbody.assign(fi.begin(), fi.begin() + tail);
+    // rho of the interior pivots, until negligible; the last segment's last row apart
+    std::vector<double> rho(L);
+    double mx = 0.0;
+    for (int j = 0; j < L; ++j) {
+        rho[j] = (j == 0) ? fi[0] : -fi[j] * rho[j - 1];
+        mx = std::max(mx, std::fabs(rho[j]));
+    }
+    int rl = L;
+    while (rl > 0 && std::fabs(rho[rl - 1]) <= mx * 0x1p-60) --rl;
+    out->rho.resize(rl);
+    for (int j = 0; j < rl; ++j) out->rho[j] = (T)rho[j];
+    out->rholast = (T)((Llast > 1) ? -fl[Llast - 1] * rho[Llast - 2] : fl[0]);
+}
+
 template <typename T> void build_tables(pp_plan p, Tables& tb) {
     tb.blob.clear();
     Emit<T> em{tb.blob};
@@ -404,6 +499,8 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
     const int ks = p->zsplit;
     std::vector<std::vector<Line<T>>> blines(ks > 0 ? slots : 0);
     std::vector<T> meet(ks > 0 ? (size_t)slots * ny * 6 : 0);
+    const int nseg = p->zsegs;
+    std::vector<std::vector<SegLine<T>>> slines(nseg > 0 ? slots : 0);
     size_t rows = 0;
     for (int m = 0; m < slots; ++m) {
         const bool pairslot = (p->bx != pp::BC_P) || (m == 0);
@@ -431,6 +528,17 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
                     const bool pinned = p->singular && m == 0 && e == 0 && part == 0;
                     pivots<T>(lamx[kx] + lamy[ky], nz, p->h[2], p->bz0, p->bz1, pinned, &ln, ks - 1, &wk);
                 }
+                if (nseg > 0) {
+                    if (slines[m].empty()) slines[m].resize((size_t)ny * 2);
+                    SegLine<T>& sl = slines[m][(size_t)e * 2 + part];
+                    if (kx >= 0) {
+                        const bool pinned = p->singular && m == 0 && e == 0 && part == 0;
+                        seg_line<T>(lamx[kx] + lamy[ky], nz, p->h[2], p->bz0, p->bz1, pinned, p->zseglen, nseg, &sl);
+                    } else {
+                        // padding part: zero right-hand side; any non-singular values
+                        sl.k[0][3] = sl.k[1][3] = sl.k[2][3] = 0.0;
+                    }
+                }
                 if (ks > 0) {
                     if (blines[m].empty()) blines[m].resize((size_t)ny * 2);
                     Line<T>& bl = blines[m][(size_t)e * 2 + part];
@@ -439,6 +547,7 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
                     mt[part] = (T)wk;
                     mt[2 + part] = (T)vk;
                     mt[4 + part] = (T)(1.0 / (1.0 - vk * wk));
+                    if (kx >= 0) p->split_gmax = std::max(p->split_gmax, std::fabs(1.0 / (1.0 - vk * wk)));
                 }
                 winf[((size_t)m * ny + e) * 2 + part] = ln.winf;
                 wlast[((size_t)m * ny + e) * 2 + part] = ln.wlast;
@@ -517,6 +626,73 @@ template <typename T> void build_tables(pp_plan p, Tables& tb) {
                     }
         tb.t_meet = em.put(sizeof(T) * meet.size());
         std::memcpy(tb.blob.data() + tb.t_meet, meet.data(), sizeof(T) * meet.size());
+    }
+    if (nseg > 0) {
+        // the segmented march's tables, laid out as the top-down ones
+        auto emit_seg_rows = [&](std::vector<T> SegLine<T>::*vec, T SegLine<T>::*inf, size_t* t_off, size_t* t_len,
+                                 size_t* t_rows, size_t* t_inf) {
+            std::vector<int> off(slots), len((size_t)slots * ny);
+            std::vector<T> vinf((size_t)slots * ny * 2);
+            size_t nrows = 0;
+            std::vector<int> lm(slots);
+            for (int m = 0; m < slots; ++m) {
+                int l = 0;
+                for (int e = 0; e < ny; ++e) {
+                    int el = 0;
+                    for (int part = 0; part < 2; ++part) {
+                        const SegLine<T>& sl = slines[m][(size_t)e * 2 + part];
+                        el = std::max(el, (int)(sl.*vec).size());
+                        if (inf) vinf[((size_t)m * ny + e) * 2 + part] = sl.*inf;
+                    }
+                    len[(size_t)m * ny + e] = el;
+                    l = std::max(l, el);
+                }
+                off[m] = (int)nrows;
+                lm[m] = l;
+                nrows += l;
+            }
+            *t_off = em.put(sizeof(int) * slots);
+            std::memcpy(tb.blob.data() + *t_off, off.data(), sizeof(int) * slots);
+            *t_len = em.put(sizeof(int) * len.size());
+            std::memcpy(tb.blob.data() + *t_len, len.data(), sizeof(int) * len.size());
+            if (t_inf) {
+                *t_inf = em.put(sizeof(T) * vinf.size());
+                std::memcpy(tb.blob.data() + *t_inf, vinf.data(), sizeof(T) * vinf.size());
+            }
+            *t_rows = em.put(sizeof(T) * 2 * std::max<size_t>(nrows, 1) * ny);
+            T* rr = reinterpret_cast<T*>(tb.blob.data() + *t_rows);
+            for (int m = 0; m < slots; ++m)
+                for (int j = 0; j < lm[m]; ++j)
+                    for (int e = 0; e < ny; ++e)
+                        for (int part = 0; part < 2; ++part) {
+                            const SegLine<T>& sl = slines[m][(size_t)e * 2 + part];
+                            const std::vector<T>& v = sl.*vec;
+                            // past its stored rows: the pivots' converged value, rho's zero
+                            const T past = inf ? sl.*inf : T(0);
+                            rr[((size_t)(off[m] + j) * ny + e) * 2 + part] = (j < (int)v.size()) ? v[j] : past;
+                        }
+        };
+        emit_seg_rows(&SegLine<T>::fbody, &SegLine<T>::finf, &tb.t_frowoff, &tb.t_felen, &tb.t_fwrows, &tb.t_fwinf);
+        emit_seg_rows(&SegLine<T>::rho, nullptr, &tb.t_rrowoff, &tb.t_relen, &tb.t_rrows, nullptr);
+        auto emit_pair = [&](T SegLine<T>::*field, size_t* t) {
+            *t = em.put(sizeof(T) * 2 * (size_t)slots * ny);
+            T* v = reinterpret_cast<T*>(tb.blob.data() + *t);
+            for (int m = 0; m < slots; ++m)
+                for (int e = 0; e < ny; ++e)
+                    for (int part = 0; part < 2; ++part)
+                        v[((size_t)m * ny + e) * 2 + part] = slines[m][(size_t)e * 2 + part].*field;
+        };
+        emit_pair(&SegLine<T>::flast, &tb.t_flast);
+        emit_pair(&SegLine<T>::rholast, &tb.t_rholast);
+        tb.t_segk = em.put(sizeof(T) * 2 * 12 * (size_t)slots * ny);
+        T* kk = reinterpret_cast<T*>(tb.blob.data() + tb.t_segk);
+        for (int m = 0; m < slots; ++m)
+            for (int e = 0; e < ny; ++e)
+                for (int c = 0; c < 3; ++c)
+                    for (int i = 0; i < 4; ++i)
+                        for (int part = 0; part < 2; ++part)
+                            kk[(((size_t)m * ny + e) * 12 + c * 4 + i) * 2 + part] =
+                                (T)slines[m][(size_t)e * 2 + part].k[c][i];
     }
     // interior diagonal hz^2 lam - 2 of every z-system (PCR); padding parts get a
     // harmless non-singular value (their right-hand side is zero)
@@ -717,7 +893,8 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
     a.zsplit = 0;
     const long long cols = (long long)p->slots * p->batch, cus = pp::device_cus();
     const long long lim = p->dtype == PP_F64 ? cus / 2 : (p->dtype == PP_F32 ? 2 * cus : 4 * cus);
-    const bool split = p->zsplit_mode == PP_ZSPLIT_ON || (p->zsplit_mode == PP_ZSPLIT_AUTO && cols <= lim);
+    const bool split = p->zsplit_mode == PP_ZSPLIT_ON ||
+                       (p->zsplit_mode == PP_ZSPLIT_AUTO && cols <= lim && p->split_gmax <= kSplitGMax);
     if (p->zsplit > 0 && p->zsolver == 0 && split) {
         a.zsplit = p->zsplit;
         a.browoff = reinterpret_cast<const int*>(t + tb.t_browoff);
@@ -726,6 +903,29 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
         a.bwrows = reinterpret_cast<const cplx<T>*>(t + tb.t_bwrows);
         a.meet = reinterpret_cast<const cplx<T>*>(t + tb.t_meet);
         a.zbuf = reinterpret_cast<cplx<T>*>(ws + p->o_zb[set]);
+    }
+    // the segmented march where the plan has one (f64 and f32 plans with few
+    // columns), unless a layout is forced
+    a.zsegs = 0;
+    if (p->zsegs > 0 && p->zsolver == 0 &&
+        (p->zsplit_mode == PP_ZSPLIT_SEG || (p->zsplit_mode == PP_ZSPLIT_AUTO && a.zsplit > 0))) {
+        a.zsplit = 0;
+        a.zsegs = p->zsegs;
+        a.zseglen = p->zseglen;
+        a.frowoff = reinterpret_cast<const int*>(t + tb.t_frowoff);
+        a.felen = reinterpret_cast<const int*>(t + tb.t_felen);
+        a.fwrows = reinterpret_cast<const cplx<T>*>(t + tb.t_fwrows);
+        a.fwinf = reinterpret_cast<const cplx<T>*>(t + tb.t_fwinf);
+        a.flast = reinterpret_cast<const cplx<T>*>(t + tb.t_flast);
+        a.rrowoff = reinterpret_cast<const int*>(t + tb.t_rrowoff);
+        a.relen = reinterpret_cast<const int*>(t + tb.t_relen);
+        a.rrows = reinterpret_cast<const cplx<T>*>(t + tb.t_rrows);
+        a.rholast = reinterpret_cast<const cplx<T>*>(t + tb.t_rholast);
+        a.segk = reinterpret_cast<const cplx<T>*>(t + tb.t_segk);
+        const size_t unit = (size_t)p->batch * p->slots * p->zsegs * p->ny;
+        a.segg = reinterpret_cast<cplx<T>*>(ws + p->o_seg);
+        a.segw = a.segg + 2 * unit;
+        a.seglr = a.segw + 4 * unit;
     }
     a.zsolver = p->zsolver;
     a.bz0 = p->bz0;
@@ -1156,6 +1356,22 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         const int kz = pp::zpipe_planes(ny, f64);
         const int nch = kz > 0 ? (nz + kz - 1) / kz : 0;
         if (p->bz0 != pp::BC_P && kz > 0 && nz >= 2 * kz) p->zsplit = kz * ((nch + 1) / 2);
+        // segmented march (f64 and f32 plans): enough segments per column to
+        // give MI355X's 256 CUs a workgroup each, of whole chunks, at least two
+        // chunks long; only where that means three segments or more
+        if (p->zsplit > 0 && dtype != PP_F32_REFINED) {
+            const long long cols = (long long)p->slots * batch;
+            int nseg = (int)std::min<long long>(kMaxSegments, kSegTargetColumns / std::max<long long>(cols, 1));
+            if (nseg >= 3) {
+                int len = (nz + nseg - 1) / nseg;
+                len = std::max(2 * kz, (len + kz - 1) / kz * kz);
+                nseg = (nz + len - 1) / len;
+                if (nseg >= 3) {
+                    p->zsegs = nseg;
+                    p->zseglen = len;
+                }
+            }
+        }
     }
     if (f64) build_tables<double>(p, p->tb[0]);
     else build_tables<float>(p, p->tb[0]);
@@ -1183,6 +1399,12 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     if (dtype == PP_F32_REFINED) off = align_up(off + sizeof(float) * n * batch);
     p->o_lo = off;
     off = align_up(off + sizeof(cplx<double>) * (size_t)batch * p->nlo * nz * ny);
+    if (p->zsegs > 0) {
+        // segment end values (2 per segment), reduction scratch (4 per
+        // segment) and couplings (2 per segment), per (batch, slot, entry)
+        p->o_seg = off;
+        off = align_up(off + p->elem * (size_t)batch * p->slots * ny * p->zsegs * 8);
+    }
     if (p->zsplit > 0) {
         for (int i = 0; i < p->ntab; ++i) {
             p->o_zb[i] = off;
@@ -1214,8 +1436,10 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver) {
 }
 
 pp_status pp_plan_set_zsplit(pp_plan p, pp_zsplit mode) {
-    if (!p || (mode != PP_ZSPLIT_AUTO && mode != PP_ZSPLIT_OFF && mode != PP_ZSPLIT_ON)) return PP_ERR_ARG;
+    if (!p || (mode != PP_ZSPLIT_AUTO && mode != PP_ZSPLIT_OFF && mode != PP_ZSPLIT_ON && mode != PP_ZSPLIT_SEG))
+        return PP_ERR_ARG;
     if (mode == PP_ZSPLIT_ON && p->zsplit == 0) return (p->bz0 == pp::BC_P) ? PP_ERR_BC : PP_ERR_SIZE;
+    if (mode == PP_ZSPLIT_SEG && p->zsegs == 0) return (p->bz0 == pp::BC_P) ? PP_ERR_BC : PP_ERR_SIZE;
     p->zsplit_mode = (int)mode;
     return PP_OK;
 }

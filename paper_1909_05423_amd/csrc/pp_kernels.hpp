@@ -139,6 +139,25 @@ template <typename T> struct MidArgs {
     const cplx<T>* bwinf;
     const cplx<T>* meet;     // [slot][ny][3]: w of row zsplit-1, v of row zsplit, 1 / (1 - v w)
     cplx<T>* zbuf;           // [batch][slot][2][ny]: last eliminated value of each half
+    // segmented march (zsegs >= 3): segment s holds rows [s zseglen, ...), the
+    // last one the remainder; each segment eliminated on its own (fresh
+    // pivots outside segment 0, the last row of the last segment with the
+    // bottom face), its couplings to the neighbouring segments solved from the
+    // segments' end values, then applied on the way back
+    int zsegs, zseglen;
+    const int* frowoff;      // fresh pivots, as rowoff / elen / wrows / winf
+    const int* felen;
+    const cplx<T>* fwrows;
+    const cplx<T>* fwinf;
+    const cplx<T>* flast;    // [slot][ny] last row of the last segment
+    const int* rrowoff;      // rho (fresh elimination of a segment's first unit vector) rows
+    const int* relen;
+    const cplx<T>* rrows;
+    const cplx<T>* rholast;  // [slot][ny] rho at the last row of the last segment
+    const cplx<T>* segk;     // [slot][ny][3 classes][4]: p_first, p_last, q_first, q_last
+    cplx<T>* segg;           // [batch][slot][zsegs][2][ny]: segment end values (local solution)
+    cplx<T>* segw;           // [batch][slot][zsegs][4][ny]: reduction scratch
+    cplx<T>* seglr;          // [batch][slot][zsegs][2][ny]: couplings above / below each segment
     // periodic z (Sherman-Morrison, see the plan code): per slot, rows of
     // alpha = first row of the inverse of the split matrix and of the
     // forward-eliminated rank-one vector; per entry its last value, 1/den, 1/gamma

@@ -389,15 +389,26 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     const int m = blockIdx.x, b = blockIdx.y;
     const int ny = FULL ? NYMAX : a.ny;
     static_assert(PH == 0 || !PERZ, "periodic z is one march");
-    const int side = PH ? (int)blockIdx.z : 0;
-    const int nz = PH ? (side ? a.nz - a.zsplit : a.zsplit) : a.nz;   // rows of this march, in local order
+    constexpr bool TWO = (PH == 1 || PH == 2);   // two-sided split
+    constexpr bool SEG = (PH == 3 || PH == 4);   // segmented
+    const int side = TWO ? (int)blockIdx.z : 0;
+    const int seg = SEG ? (int)blockIdx.z : 0;
+    const bool lastseg = SEG && seg == a.zsegs - 1;
+    const bool fresh = SEG && seg > 0;            // pivots of a segment starting inside the column
+    const int a0 = SEG ? seg * a.zseglen : 0;
+    // rows of this march, in local order
+    const int nz = SEG ? (lastseg ? a.nz - a0 : a.zseglen) : (TWO ? (side ? a.nz - a.zsplit : a.zsplit) : a.nz);
     if (side) {
         icol += (ptrdiff_t)(a.nz - 1) * izs;
         ocol += (ptrdiff_t)(a.nz - 1) * zs;
         izs = -izs;
         zs = -zs;
     }
-    const cplx<T>* wrows = side ? a.bwrows : a.wrows;
+    if (SEG) {
+        icol += (ptrdiff_t)a0 * izs;
+        ocol += (ptrdiff_t)a0 * zs;
+    }
+    const cplx<T>* wrows = side ? a.bwrows : (fresh ? a.fwrows : a.wrows);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -422,7 +433,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     const bool pairslot = (a.bx != BC_P) || (m == 0);
     const bool sep = (a.by == BC_P) && pairslot;
     const bool sing = a.singular && (m == 0);
-    const int roff = side ? a.browoff[m] : a.rowoff[m];
+    const int roff = side ? a.browoff[m] : (fresh ? a.frowoff[m] : a.rowoff[m]);
     const T scale = a.scale;
     const T proj = (sing && a.project) ? (T)(a.hz2 * a.mu[b]) : T(0);
     const int half = (ny >> 1) + 1;
@@ -450,9 +461,9 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
         const int e = tid + NTH * o;
         live[o] = FULL || e < ny;
         ec[o] = live[o] ? e : 0;
-        winf[o] = (side ? a.bwinf : a.winf)[(size_t)m * ny + ec[o]];
-        elen[o] = (side ? a.belen : a.elen)[(size_t)m * ny + ec[o]];
-        wlast[o] = a.wlast[(size_t)m * ny + ec[o]];
+        winf[o] = (side ? a.bwinf : (fresh ? a.fwinf : a.winf))[(size_t)m * ny + ec[o]];
+        elen[o] = (side ? a.belen : (fresh ? a.felen : a.elen))[(size_t)m * ny + ec[o]];
+        wlast[o] = (lastseg ? a.flast : a.wlast)[(size_t)m * ny + ec[o]];
         y0[o] = mk<T>(T(0), T(0));
         corr[o] = y0[o];
         qnext[o] = y0[o];
@@ -491,7 +502,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     // (component-wise selects between values, so that the arrays stay in registers)
     auto pivot = [&](int z, int l, int o) __attribute__((always_inline)) -> cplx<T> {
         const cplx<T> p = pv[l * OWN + o], wi = winf[o], wl = wlast[o];
-        const bool lastrow = (PH == 0) && (z == nz - 1), tab = (z < elen[o]);
+        const bool lastrow = (PH == 0 || lastseg) && (z == nz - 1), tab = (z < elen[o]);
         return mk<T>(lastrow ? wl.x : (tab ? p.x : wi.x), lastrow ? wl.y : (tab ? p.y : wi.y));
     };
     // upward prefetch (clamped to the last plane): YFWD, elements y = lane + 64 k
@@ -525,12 +536,22 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
 
     // ------------------------------------------------------------- upward
     cplx<T> st[OWN];
+    // segmented march: the segment's local solution at its first row,
+    // sum_z tau_z y_z with tau the back substitution's running product
+    cplx<T> ga[PH == 3 ? OWN : 1], tau[PH == 3 ? OWN : 1];
 #pragma unroll
     for (int o = 0; o < OWN; ++o) st[o] = mk<T>(T(0), T(0));
+    if constexpr (PH == 3) {
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            ga[o] = mk<T>(T(0), T(0));
+            tau[o] = mk<T>(T(1), T(1));
+        }
+    }
     // the split march's float halves load each chunk's pivots just before its
     // recurrences (registers: their prefetch would be live across the transforms)
     constexpr bool LATEPIV = PH != 0 && sizeof(Tf) == 4 && sizeof(T) == 4;
-    if constexpr (PH != 2) {
+    if constexpr (PH != 2 && PH != 4) {
         load_plane(0);
         if constexpr (!LATEPIV) load_piv(0);
     }
@@ -646,6 +667,10 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
                     }
                     prev = mk<T>((d.x - prev.x) * w.x, (d.y - prev.y) * w.y);
                     ocol[(ptrdiff_t)z * zs + e] = cvt<Tout>(prev);
+                    if constexpr (PH == 3) {
+                        ga[o] = mk<T>(ga[o].x + tau[o].x * prev.x, ga[o].y + tau[o].y * prev.y);
+                        tau[o] = mk<T>(-w.x * tau[o].x, -w.y * tau[o].y);
+                    }
                 }
             }
             st[o] = prev;
@@ -654,7 +679,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     };
     // the first chunk is issued outside the loop so that every pass through the
     // loop sees the same sequence of memory operations before it
-    if constexpr (PH != 2) {
+    if constexpr (PH != 2 && PH != 4) {
         up_chunk(0);
         for (int c = 1; c < nchunks; ++c) up_chunk(c);
     }
@@ -666,11 +691,24 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
         if (side == 0 && m == 0 && tid == 0) a.cmean[b] = 0.0;   // the halves add their shares in PH 2
         return;
     }
+    if constexpr (PH == 3) {
+        // the segment's local solution at its first and last rows (the last
+        // is the last eliminated value), for the reduced system
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            if (!live[o]) continue;
+            cplx<T>* g = a.segg + (((size_t)b * a.slots + m) * a.zsegs + seg) * 2 * ny + ec[o];
+            g[0] = ga[o];
+            g[ny] = st[o];
+        }
+        if (seg == 0 && m == 0 && tid == 0) a.cmean[b] = 0.0;   // the segments add their shares in PH 4
+        return;
+    }
 
     // ----------------------------------------------------------- downward
     // the top chunk's eliminated right-hand sides were stored by this thread
     // (same entries, same addresses): read them back in program order
-    if constexpr (PH == 2 && !LATEPIV) load_piv(last);
+    if constexpr ((PH == 2 || PH == 4) && !LATEPIV) load_piv(last);
     load_entry(last);
 #pragma unroll
     for (int o = 0; o < OWN; ++o) {
@@ -694,6 +732,26 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
             st[o] = mk<T>(T(0), T(0));
         }
     }
+    // segmented march: the couplings above (cl) and below (cr) this segment,
+    // and the rows of rho (per entry: rel, wavefront maximum: rlw)
+    cplx<T> cl[PH == 4 ? OWN : 1], cr[PH == 4 ? OWN : 1], rhol[PH == 4 ? OWN : 1];
+    int rel[PH == 4 ? OWN : 1], rlw[PH == 4 ? OWN : 1];
+    int rroff = 0;
+    if constexpr (PH == 4) {
+        rroff = fresh ? a.rrowoff[m] : 0;
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const cplx<T>* lr = a.seglr + (((size_t)b * a.slots + m) * a.zsegs + seg) * 2 * ny + ec[o];
+            cl[o] = lr[0];
+            cr[o] = lr[ny];
+            rhol[o] = a.rholast[(size_t)m * ny + ec[o]];
+            rel[o] = (fresh && live[o]) ? a.relen[(size_t)m * ny + ec[o]] : 0;
+            int x = rel[o];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+            rlw[o] = __builtin_amdgcn_readfirstlane(x);
+        }
+    }
     double csum = 0.0;
     auto down_chunk = [&](int c) __attribute__((always_inline)) {
         const int zc = c * kSZ;
@@ -713,6 +771,14 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
                         qv[l] = (zc + l < qel[o]) ? a.qrows[(size_t)(qoff + zc + l) * ny + e] : mk<T>(T(0), T(0));
                 }
             }
+            cplx<T> rv[PH == 4 ? kSZ : 1];
+            if constexpr (PH == 4) {
+                if (zc < rlw[o]) {
+#pragma unroll
+                    for (int l = 0; l < kSZ; ++l)
+                        rv[l] = (zc + l < rel[o]) ? a.rrows[(size_t)(rroff + zc + l) * ny + e] : mk<T>(T(0), T(0));
+                }
+            }
             cplx<T> nxt = st[o];
 #pragma unroll
             for (int j = 0; j < kSZ; ++j) {
@@ -720,7 +786,18 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
                 if (FULL || l < nl) {
                     const int z = zc + l;
                     const cplx<T> w = pivot(z, l, o);
-                    const cplx<T> dp = pre[l * OWN + o];
+                    cplx<T> dp = pre[l * OWN + o];
+                    if constexpr (PH == 4) {
+                        // the couplings moved to the right-hand side: the row
+                        // above the segment through rho, the row below it at the
+                        // segment's last row through that row's pivot
+                        if (fresh) {
+                            cplx<T> r = (zc < rlw[o]) ? rv[l] : mk<T>(T(0), T(0));
+                            if (lastseg && z == nz - 1) r = rhol[o];
+                            dp = mk<T>(dp.x - cl[o].x * r.x, dp.y - cl[o].y * r.y);
+                        }
+                        if (!lastseg && z == nz - 1) dp = mk<T>(dp.x - cr[o].x * w.x, dp.y - cr[o].y * w.y);
+                    }
                     nxt = mk<T>(dp.x - w.x * nxt.x, dp.y - w.y * nxt.y);
                     cplx<T> un = nxt;
                     if constexpr (PERZ) {
@@ -793,7 +870,7 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
     };
     down_chunk(nchunks - 1);
     for (int c = nchunks - 2; c >= 0; --c) down_chunk(c);
-    if constexpr (PH == 2) {
+    if constexpr (PH == 2 || PH == 4) {
         if (m == 0 && tid == 0 && sing && a.demean) atomicAdd(&a.cmean[b], csum / (double)a.nz);
     } else {
         if (m == 0 && tid == 0) a.cmean[b] = (sing && a.demean) ? csum / (double)nz : 0.0;
@@ -906,16 +983,84 @@ __global__ __launch_bounds__(64 * kYpreWaves) void k_ypre(cplx<double>* __restri
     for (int y = lane; y < ny; y += 64) src[y] = line[pad(y)];
 }
 
-// Every chunk of the march (of both halves, when split) whole.
+// Every chunk of the march (of both halves, or of every segment) whole.
 template <typename T> static bool pipe_full(const MidArgs<T>& a, int nymax, int nw) {
     if (a.ny != nymax) return false;
+    if (a.zsegs > 0) return a.zseglen % nw == 0 && (a.nz - (a.zsegs - 1) * a.zseglen) % nw == 0;
     if (a.zsplit > 0) return a.zsplit % nw == 0 && (a.nz - a.zsplit) % nw == 0;
     return a.nz % nw == 0;
+}
+
+// Segmented march, between its two launches: per (batch entry, slot, entry)
+// one thread solves the reduced system of the segments' end rows.  Segment t's
+// first and last values are X_t = Ga_t - L_t pa_t - R_t qa_t and Z_t = Gb_t -
+// L_t pb_t - R_t qb_t (G the segment's local solution, L_t = Z_{t-1} the row
+// above it, R_t = X_{t+1} the row below, p / q the responses to those rows);
+// eliminated forward as Z_t = al_t + be_t X_{t+1}, X_t = ga_t + de_t X_{t+1},
+// then solved backward from X_{P-1} = ga_{P-1}.  Each part (real system) on
+// its own.
+template <typename T> __global__ __launch_bounds__(256) void k_zseg_reduce(MidArgs<T> a, int batch) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int ny = a.ny, P = a.zsegs;
+    if (i >= (size_t)batch * a.slots * ny) return;
+    const int e = (int)(i % ny);
+    const size_t bm = i / ny;
+    const int m = (int)(bm % a.slots);
+    const cplx<T>* K = a.segk + ((size_t)m * ny + e) * 12;
+    const cplx<T>* G = a.segg + bm * P * 2 * ny + e;
+    cplx<T>* W = a.segw + bm * P * 4 * ny + e;
+    cplx<T>* LR = a.seglr + bm * P * 2 * ny + e;
+    auto kk = [&](int t, int j) { return K[(t == 0 ? 0 : (t == P - 1 ? 8 : 4)) + j]; };
+    auto mul = [](cplx<T> x, cplx<T> y) { return mk<T>(x.x * y.x, x.y * y.y); };
+    auto sub = [](cplx<T> x, cplx<T> y) { return mk<T>(x.x - y.x, x.y - y.y); };
+    auto add = [](cplx<T> x, cplx<T> y) { return mk<T>(x.x + y.x, x.y + y.y); };
+    cplx<T> al = G[ny];
+    cplx<T> be = mk<T>(-kk(0, 3).x, -kk(0, 3).y);
+    W[0] = al;
+    W[ny] = be;
+    cplx<T> ga = al, de = be;
+    for (int t = 1; t < P; ++t) {
+        const cplx<T> pa = kk(t, 0), pb = kk(t, 1), qa = kk(t, 2), qb = kk(t, 3);
+        const cplx<T> den = add(mk<T>(T(1), T(1)), mul(pa, be));
+        const cplx<T> num = sub(G[(size_t)t * 2 * ny], mul(pa, al));
+        ga = mk<T>(num.x / den.x, num.y / den.y);
+        de = mk<T>(-qa.x / den.x, -qa.y / den.y);
+        W[((size_t)t * 4 + 2) * ny] = ga;
+        W[((size_t)t * 4 + 3) * ny] = de;
+        if (t < P - 1) {
+            al = sub(G[((size_t)t * 2 + 1) * ny], mul(pb, add(al, mul(be, ga))));
+            const cplx<T> nb = add(mul(mul(pb, be), de), qb);
+            be = mk<T>(-nb.x, -nb.y);
+            W[(size_t)t * 4 * ny] = al;
+            W[((size_t)t * 4 + 1) * ny] = be;
+        }
+    }
+    cplx<T> X = ga;   // X_{P-1}
+    LR[0] = mk<T>(T(0), T(0));                          // nothing above segment 0
+    LR[((size_t)(P - 1) * 2 + 1) * ny] = mk<T>(T(0), T(0));   // nothing below the last
+    for (int t = P - 2; t >= 0; --t) {
+        const cplx<T> Z = add(W[(size_t)t * 4 * ny], mul(W[((size_t)t * 4 + 1) * ny], X));
+        LR[((size_t)(t + 1) * 2) * ny] = Z;          // the row above segment t+1
+        LR[((size_t)t * 2 + 1) * ny] = X;            // the row below segment t
+        if (t >= 1) X = add(W[((size_t)t * 4 + 2) * ny], mul(W[((size_t)t * 4 + 3) * ny], X));
+    }
 }
 
 template <typename T, int NYMAX, int NW, bool FULL>
 static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     const dim3 block(64 * NW);
+    if (a.zsegs > 0) {    // never with periodic z
+        const dim3 grid(a.slots, batch, a.zsegs);
+        hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 3>), grid, block, 0, s, S, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const size_t nth = (size_t)batch * a.slots * a.ny;
+        hipLaunchKernelGGL(k_zseg_reduce<T>, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, a, batch);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 4>), grid, block, 0, s, S, a);
+        return hipGetLastError();
+    }
     if (a.zsplit > 0) {   // never with periodic z
         const dim3 grid(a.slots, batch, 2);
         hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 1>), grid, block, 0, s, S, a);

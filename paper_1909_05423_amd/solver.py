@@ -17,7 +17,7 @@ DTYPES = {"f64": (_lib.PP_F64, torch.float64), "f32": (_lib.PP_F32, torch.float3
           "f32_refined": (_lib.PP_F32_REFINED, torch.float64)}
 GAUGES = {"mean": _lib.PP_GAUGE_MEAN, "pin": _lib.PP_GAUGE_PIN, "pin_raw": _lib.PP_GAUGE_PIN_RAW}
 ZSOLVERS = {"thomas": 0, "pcr": 1, "cr": 2}
-ZSPLITS = {"auto": 0, "off": 1, "on": 2}
+ZSPLITS = {"auto": 0, "off": 1, "on": 2, "seg": 3}
 
 
 class Plan:

@@ -91,3 +91,82 @@ def test_split_many_columns_and_adjoint():
     assert rel_max(us, oracle.solve(f, bc, h, "mean")) < 1e-12
     ua, _ = _solve(f, bc, h, "f64", "on", adjoint=True)
     assert rel_max(ua, oracle.solve_adjoint(f, bc, h, "mean")) < 1e-12
+
+
+# Segmented march (three or more segments per column; plans with few columns):
+# (64, 12, 16) four whole segments, (100, 9, 6) seven with a ragged last one,
+# (61, 24, 27) four, (48, 384, 4) three in double and four in float.
+SEG_SHAPES = [(64, 12, 16), (100, 9, 6), (61, 24, 27), (48, 384, 4)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["DDDDDD", "PPPPDN", "NNDDND", "PPNNDD", "DDPPNN"])
+def test_segmented_vs_oracle_and_single_march(dtype, bc):
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(3 + sum(map(ord, bc + dtype)))
+    for shape in SEG_SHAPES:
+        banner(f"segmented {dtype} {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = _input(rng, shape, dtype)
+        us, _ = _solve(f, bc, h, dtype, "seg")
+        u1, _ = _solve(f, bc, h, dtype, "off")
+        uo = oracle.solve(f, bc, h, "mean")
+        assert rel_max(us, uo) < TOL[dtype], (dtype, bc, shape)
+        assert rel_max(us, u1) < TOL[dtype], (dtype, bc, shape)
+
+
+@pytest.mark.parametrize("bc", ["PPPPNN", "NNNNNN", "NNPPNN"])
+@pytest.mark.parametrize("gauge", ["mean", "pin", "pin_raw"])
+def test_segmented_singular_gauges_batch(bc, gauge):
+    """The pinned zero-mode line in segment 0 and the zero-mode mean the
+    segments add up, per batch entry."""
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(15)
+    for shape in [(64, 12, 16), (70, 18, 9)]:
+        banner(f"segmented gauge {gauge} {bc} {shape}")
+        h = tuple(rng.uniform(0.5, 2.0, 3))
+        f = rng.standard_normal((3,) + shape) + np.array([0.3, -1.0, 2.0])[:, None, None, None]
+        us, plan = _solve(f, bc, h, "f64", "seg", gauge=gauge, batch=3)
+        _, means, _ = plan.last_info()
+        for b in range(3):
+            uo = oracle.solve(f[b], bc, h, gauge)
+            assert rel_max(us[b], uo) < 1e-12, (b, gauge, bc, shape)
+            expect = f[b].mean() if gauge != "pin_raw" else 0.0
+            assert abs(means[b] - expect) < 1e-13 * max(1.0, abs(f[b]).max())
+
+
+def test_segmented_long_columns_and_adjoint():
+    """The paper's solver-comparison shape family (few columns, long z), with
+    Dirichlet x: no z-system close to singular."""
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(21)
+    for shape in [(1023, 16, 16), (255, 64, 8)]:
+        bc = "DDPPNN"
+        h = (1.0 / 64, 1.0 / 64, 1.0 / 64)
+        f = rng.standard_normal(shape)
+        banner(f"segmented long {shape}")
+        us, _ = _solve(f, bc, h, "f64", "seg")
+        assert rel_max(us, oracle.solve(f, bc, h, "mean")) < 1e-12
+        ua, _ = _solve(f, bc, h, "f64", "seg", adjoint=True)
+        assert rel_max(ua, oracle.solve_adjoint(f, bc, h, "mean")) < 1e-12
+
+
+def test_auto_keeps_near_singular_columns_whole():
+    """Long columns under periodic x, y and Neumann z: splitting the zero
+    mode's system would amplify rounding by about nz / 2, so the automatic
+    layout keeps one march per column and meets the 1e-12 bar; the forced
+    splits stay within the bound the header states (amplification times the
+    unit roundoff)."""
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(23)
+    shape, bc = (1023, 16, 16), "PPPPNN"
+    h = (1.0 / 64, 1.0 / 64, 1.0 / 64)
+    f = rng.standard_normal(shape)
+    uo = oracle.solve(f, bc, h, "mean")
+    banner(f"auto near-singular {shape}")
+    u, _ = _solve(f, bc, h, "f64", "auto")
+    assert rel_max(u, uo) < 1e-12
+    for zs in ("on", "seg"):
+        us, _ = _solve(f, bc, h, "f64", zs)
+        assert rel_max(us, uo) < 512 * 2.2e-16 * 64, zs
+

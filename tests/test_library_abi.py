@@ -162,7 +162,8 @@ def test_zsplit_option(lib):
     assert st == 0
     for mode in (0, 1, 2, 0):
         assert lib.pp_plan_set_zsplit(p, mode) == 0
-    assert lib.pp_plan_set_zsplit(p, 3) == -1
+    assert lib.pp_plan_set_zsplit(p, 3) == -3     # 16 planes: no room for three segments
+    assert lib.pp_plan_set_zsplit(p, 4) == -1
     assert lib.pp_plan_set_zsplit(p, -1) == -1
     lib.pp_plan_destroy(p)
     for nx, ny, nz, bc, want in [(8, 8, 16, "PPPPPP", -2),     # periodic z: one march
@@ -171,7 +172,13 @@ def test_zsplit_option(lib):
                                  (8, 384, 12, "PPPPDD", -3)]:  # double lines of 384: chunks of 8
         st, p = _create(lib, nx, ny, nz, bc)
         assert st == 0 and lib.pp_plan_set_zsplit(p, 2) == want, (nx, ny, nz, bc)
+        assert lib.pp_plan_set_zsplit(p, 3) == want, (nx, ny, nz, bc)
         assert lib.pp_plan_set_zsplit(p, 1) == 0 and lib.pp_plan_set_zsplit(p, 0) == 0
+        lib.pp_plan_destroy(p)
+    # segments: few columns and z long enough for three of at least two chunks
+    for nx, nz, dtype, want in [(16, 48, 0, 0), (16, 33, 0, 0), (16, 32, 0, -3), (16, 48, 2, -3), (512, 4096, 0, -3)]:
+        st, p = _create(lib, nx, 8, nz, "PPPPDD", dtype=dtype)
+        assert st == 0 and lib.pp_plan_set_zsplit(p, 3) == want, (nx, nz, dtype)
         lib.pp_plan_destroy(p)
 
 
