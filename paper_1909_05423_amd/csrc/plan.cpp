@@ -893,8 +893,13 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
     a.zsplit = 0;
     const long long cols = (long long)p->slots * p->batch, cus = pp::device_cus();
     const long long lim = p->dtype == PP_F64 ? cus / 2 : (p->dtype == PP_F32 ? 2 * cus : 4 * cus);
+    // the amplification bound holds double plans to the single march's
+    // accuracy; float rounding (6e-8) dominates the two-way split's meeting
+    // rows (512^3 periodic x, y: 1.97e-6 split, 1.81e-6 whole, from the f64
+    // solve) but not the segmented march's (1023 x 16 x 16: 3.7e-5 vs 1.5e-6)
+    const bool tame = p->split_gmax <= kSplitGMax;
     const bool split = p->zsplit_mode == PP_ZSPLIT_ON ||
-                       (p->zsplit_mode == PP_ZSPLIT_AUTO && cols <= lim && p->split_gmax <= kSplitGMax);
+                       (p->zsplit_mode == PP_ZSPLIT_AUTO && cols <= lim && (p->dtype != PP_F64 || tame));
     if (p->zsplit > 0 && p->zsolver == 0 && split) {
         a.zsplit = p->zsplit;
         a.browoff = reinterpret_cast<const int*>(t + tb.t_browoff);
@@ -908,7 +913,7 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
     // columns), unless a layout is forced
     a.zsegs = 0;
     if (p->zsegs > 0 && p->zsolver == 0 &&
-        (p->zsplit_mode == PP_ZSPLIT_SEG || (p->zsplit_mode == PP_ZSPLIT_AUTO && a.zsplit > 0))) {
+        (p->zsplit_mode == PP_ZSPLIT_SEG || (p->zsplit_mode == PP_ZSPLIT_AUTO && a.zsplit > 0 && tame))) {
         a.zsplit = 0;
         a.zsegs = p->zsegs;
         a.zseglen = p->zseglen;

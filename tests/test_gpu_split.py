@@ -154,9 +154,9 @@ def test_segmented_long_columns_and_adjoint():
 def test_auto_keeps_near_singular_columns_whole():
     """Long columns under periodic x, y and Neumann z: splitting the zero
     mode's system would amplify rounding by about nz / 2, so the automatic
-    layout keeps one march per column and meets the 1e-12 bar; the forced
-    splits stay within the bound the header states (amplification times the
-    unit roundoff)."""
+    layout keeps one march per column in double and meets the 1e-12 bar; the
+    forced splits stay within the bound the header states (amplification
+    times the unit roundoff).  Float plans keep the two-way split."""
     from gpu_util import banner, rel_max
     rng = np.random.default_rng(23)
     shape, bc = (1023, 16, 16), "PPPPNN"
@@ -169,4 +169,11 @@ def test_auto_keeps_near_singular_columns_whole():
     for zs in ("on", "seg"):
         us, _ = _solve(f, bc, h, "f64", zs)
         assert rel_max(us, uo) < 512 * 2.2e-16 * 64, zs
+    # float: the two-way split stays (float rounding dominates its meeting
+    # rows), the segments go; same kernels as the forced split, so the same bits
+    f32 = f.astype(np.float32).astype(np.float64)
+    u32, _ = _solve(f32, bc, h, "f32", "auto")
+    u32_on, _ = _solve(f32, bc, h, "f32", "on")
+    assert np.array_equal(u32, u32_on)
+    assert rel_max(u32, oracle.solve(f32, bc, h, "mean")) < 1e-5
 
