@@ -88,7 +88,7 @@ typedef enum {
  * PP_F32_REFINED; 16 B with rows over 512) or 4 B (PP_F32) per grid point and
  * batch entry, plus the plan tables (and, for the split march below, two
  * values per (x-wavenumber slot, y entry, batch entry), for the segmented
- * march eight per (slot, y entry, batch entry, segment)). */
+ * march four per (slot, y entry, batch entry, segment)). */
 
 /* Create a plan (host only; no GPU call).
  *   nx, ny, nz  cells per direction, >= 1.  nx and ny must factor as 2^a 3^b.

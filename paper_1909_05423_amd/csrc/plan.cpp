@@ -116,8 +116,12 @@ namespace {
 constexpr size_t kAlign = 256;
 // segmented march: at most this many segments per column, and segments enough
 // for this many workgroups (the compute units of an MI355X)
-constexpr int kMaxSegments = 16;
+constexpr int kMaxSegments = pp::kMaxZSegments;
 constexpr long long kSegTargetColumns = 256;
+// y lines up to 256 run a march of four wavefronts (27 KB of LDS in double),
+// several workgroups per CU: segments enough for three per CU in double (the
+// registers it takes) and four in float
+constexpr long long kSegTargetNarrowF64 = 768, kSegTargetNarrowF32 = 1024;
 // the automatic choice splits columns only where the meeting rows amplify
 // rounding by at most this much (measured: errors near 2.5e-15 times it)
 constexpr double kSplitGMax = 256.0;
@@ -929,8 +933,7 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
         a.segk = reinterpret_cast<const cplx<T>*>(t + tb.t_segk);
         const size_t unit = (size_t)p->batch * p->slots * p->zsegs * p->ny;
         a.segg = reinterpret_cast<cplx<T>*>(ws + p->o_seg);
-        a.segw = a.segg + 2 * unit;
-        a.seglr = a.segw + 4 * unit;
+        a.seglr = a.segg + 2 * unit;
     }
     a.zsolver = p->zsolver;
     a.bz0 = p->bz0;
@@ -1366,7 +1369,9 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
         // chunks long; only where that means three segments or more
         if (p->zsplit > 0 && dtype != PP_F32_REFINED) {
             const long long cols = (long long)p->slots * batch;
-            int nseg = (int)std::min<long long>(kMaxSegments, kSegTargetColumns / std::max<long long>(cols, 1));
+            const long long target =
+                ny <= 256 ? (f64 ? kSegTargetNarrowF64 : kSegTargetNarrowF32) : kSegTargetColumns;
+            int nseg = (int)std::min<long long>(kMaxSegments, target / std::max<long long>(cols, 1));
             if (nseg >= 3) {
                 int len = (nz + nseg - 1) / nseg;
                 len = std::max(2 * kz, (len + kz - 1) / kz * kz);
@@ -1405,10 +1410,10 @@ pp_status pp_plan_create(int nx, int ny, int nz, const char bc[6], const double 
     p->o_lo = off;
     off = align_up(off + sizeof(cplx<double>) * (size_t)batch * p->nlo * nz * ny);
     if (p->zsegs > 0) {
-        // segment end values (2 per segment), reduction scratch (4 per
-        // segment) and couplings (2 per segment), per (batch, slot, entry)
+        // segment end values (2 per segment) and couplings (2 per segment),
+        // per (batch, slot, entry)
         p->o_seg = off;
-        off = align_up(off + p->elem * (size_t)batch * p->slots * ny * p->zsegs * 8);
+        off = align_up(off + p->elem * (size_t)batch * p->slots * ny * p->zsegs * 4);
     }
     if (p->zsplit > 0) {
         for (int i = 0; i < p->ntab; ++i) {

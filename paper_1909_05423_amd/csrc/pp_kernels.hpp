@@ -107,6 +107,10 @@ __device__ __forceinline__ double face_lift(const FaceArgs<Tin>& fa, int b, int 
 // of the refinement without reading u.
 enum XinvMode : int { XINV_STORE = 0, XINV_UPDATE = 1, XINV_FIRST = 2 };
 
+// segmented z march: at most this many segments per column (the reduced
+// system's kernel keeps one row per segment in registers)
+constexpr int kMaxZSegments = 16;
+
 // z-march kernel: one workgroup per (spectral x column, batch entry).
 template <typename T> struct MidArgs {
     int ny, nz, slots;
@@ -156,7 +160,6 @@ template <typename T> struct MidArgs {
     const cplx<T>* rholast;  // [slot][ny] rho at the last row of the last segment
     const cplx<T>* segk;     // [slot][ny][3 classes][4]: p_first, p_last, q_first, q_last
     cplx<T>* segg;           // [batch][slot][zsegs][2][ny]: segment end values (local solution)
-    cplx<T>* segw;           // [batch][slot][zsegs][4][ny]: reduction scratch
     cplx<T>* seglr;          // [batch][slot][zsegs][2][ny]: couplings above / below each segment
     // periodic z (Sherman-Morrison, see the plan code): per slot, rows of
     // alpha = first row of the inverse of the split matrix and of the

@@ -318,8 +318,10 @@ __global__ __launch_bounds__(NTH) void k_zmarch(cplx<T>* __restrict__ S, MidArgs
 // ---------------------------------------------------------------------------
 // Pipelined z march for y lines of up to NYMAX = 512 (NW = 8 wavefronts), of
 // exactly 384 (float, NW = 6) or of up to 1024 (float: NW = 8; double: NW = 4, so
-// that a chunk of 1024-long double planes fits in LDS): the same stages as k_zmarch, arranged so that the
-// memory traffic of one chunk overlaps the arithmetic of another.
+// that a chunk of 1024-long double planes fits in LDS), and, segmented, of up
+// to 256 (NW = 4, several workgroups per CU): the same stages as k_zmarch,
+// arranged so that the memory traffic of one chunk overlaps the arithmetic of
+// another.
 //
 // A chunk is NW planes, one per wavefront; a lane holds elements y = lane + 64 k
 // of its wavefront's plane, and a thread owns the z recurrences of entries
@@ -879,9 +881,13 @@ __device__ __forceinline__ void zpipe_body(const cplx<Tin>* icol, ptrdiff_t izs,
 
 // Waves per SIMD a march kernel is compiled for: the split march's halves in
 // float on lines up to 512 at 4 (at most 128 VGPRs: two 512-thread
-// workgroups per CU; 512^3 float march 0.51 -> 0.46 ms), everything else at 1
-// (the registers it needs).
+// workgroups per CU; 512^3 float march 0.51 -> 0.46 ms); the segmented
+// four-wavefront march of lines up to 256 at 4 in float and 3 in double (no
+// spills; 256^3 with 128 columns: float 0.143 -> 0.100 ms, double 0.182 ->
+// 0.171 ms against the split march); everything else at 1 (the registers it
+// needs).
 template <typename T, int NYMAX, int PH> constexpr int zpipe_min_waves() {
+    if (NYMAX == 256) return sizeof(T) == 4 ? 4 : 3;
     return (PH != 0 && sizeof(T) == 4 && NYMAX <= 512) ? 4 : 1;
 }
 
@@ -998,9 +1004,12 @@ template <typename T> static bool pipe_full(const MidArgs<T>& a, int nymax, int 
 // above it, R_t = X_{t+1} the row below, p / q the responses to those rows);
 // eliminated forward as Z_t = al_t + be_t X_{t+1}, X_t = ga_t + de_t X_{t+1},
 // then solved backward from X_{P-1} = ga_{P-1}.  Each part (real system) on
-// its own.
-template <typename T> __global__ __launch_bounds__(256) void k_zseg_reduce(MidArgs<T> a, int batch) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+// its own.  The forward coefficients stay in registers (loops unrolled over
+// the largest segment count, guarded by the plan's), and the launch has
+// workgroups of one wavefront, so that every CU takes a share.
+template <typename T> __global__ __launch_bounds__(64) void k_zseg_reduce(MidArgs<T> a, int batch) {
+    constexpr int PM = kMaxZSegments;
+    const size_t i = (size_t)blockIdx.x * 64 + threadIdx.x;
     const int ny = a.ny, P = a.zsegs;
     if (i >= (size_t)batch * a.slots * ny) return;
     const int e = (int)(i % ny);
@@ -1008,59 +1017,71 @@ template <typename T> __global__ __launch_bounds__(256) void k_zseg_reduce(MidAr
     const int m = (int)(bm % a.slots);
     const cplx<T>* K = a.segk + ((size_t)m * ny + e) * 12;
     const cplx<T>* G = a.segg + bm * P * 2 * ny + e;
-    cplx<T>* W = a.segw + bm * P * 4 * ny + e;
     cplx<T>* LR = a.seglr + bm * P * 2 * ny + e;
     auto kk = [&](int t, int j) { return K[(t == 0 ? 0 : (t == P - 1 ? 8 : 4)) + j]; };
     auto mul = [](cplx<T> x, cplx<T> y) { return mk<T>(x.x * y.x, x.y * y.y); };
     auto sub = [](cplx<T> x, cplx<T> y) { return mk<T>(x.x - y.x, x.y - y.y); };
     auto add = [](cplx<T> x, cplx<T> y) { return mk<T>(x.x + y.x, x.y + y.y); };
+    cplx<T> wal[PM], wbe[PM], wga[PM], wde[PM];
     cplx<T> al = G[ny];
     cplx<T> be = mk<T>(-kk(0, 3).x, -kk(0, 3).y);
-    W[0] = al;
-    W[ny] = be;
-    cplx<T> ga = al, de = be;
-    for (int t = 1; t < P; ++t) {
-        const cplx<T> pa = kk(t, 0), pb = kk(t, 1), qa = kk(t, 2), qb = kk(t, 3);
-        const cplx<T> den = add(mk<T>(T(1), T(1)), mul(pa, be));
-        const cplx<T> num = sub(G[(size_t)t * 2 * ny], mul(pa, al));
-        ga = mk<T>(num.x / den.x, num.y / den.y);
-        de = mk<T>(-qa.x / den.x, -qa.y / den.y);
-        W[((size_t)t * 4 + 2) * ny] = ga;
-        W[((size_t)t * 4 + 3) * ny] = de;
-        if (t < P - 1) {
-            al = sub(G[((size_t)t * 2 + 1) * ny], mul(pb, add(al, mul(be, ga))));
-            const cplx<T> nb = add(mul(mul(pb, be), de), qb);
-            be = mk<T>(-nb.x, -nb.y);
-            W[(size_t)t * 4 * ny] = al;
-            W[((size_t)t * 4 + 1) * ny] = be;
+    wal[0] = al;
+    wbe[0] = be;
+    cplx<T> ga = al;
+#pragma unroll
+    for (int t = 1; t < PM; ++t) {
+        wal[t] = wbe[t] = wga[t] = wde[t] = mk<T>(T(0), T(0));
+        if (t < P) {
+            const cplx<T> pa = kk(t, 0), pb = kk(t, 1), qa = kk(t, 2), qb = kk(t, 3);
+            const cplx<T> den = add(mk<T>(T(1), T(1)), mul(pa, be));
+            const cplx<T> num = sub(G[(size_t)t * 2 * ny], mul(pa, al));
+            ga = mk<T>(num.x / den.x, num.y / den.y);
+            const cplx<T> de = mk<T>(-qa.x / den.x, -qa.y / den.y);
+            wga[t] = ga;
+            wde[t] = de;
+            if (t < P - 1) {
+                al = sub(G[((size_t)t * 2 + 1) * ny], mul(pb, add(al, mul(be, ga))));
+                const cplx<T> nb = add(mul(mul(pb, be), de), qb);
+                be = mk<T>(-nb.x, -nb.y);
+                wal[t] = al;
+                wbe[t] = be;
+            }
         }
     }
     cplx<T> X = ga;   // X_{P-1}
     LR[0] = mk<T>(T(0), T(0));                          // nothing above segment 0
     LR[((size_t)(P - 1) * 2 + 1) * ny] = mk<T>(T(0), T(0));   // nothing below the last
-    for (int t = P - 2; t >= 0; --t) {
-        const cplx<T> Z = add(W[(size_t)t * 4 * ny], mul(W[((size_t)t * 4 + 1) * ny], X));
-        LR[((size_t)(t + 1) * 2) * ny] = Z;          // the row above segment t+1
-        LR[((size_t)t * 2 + 1) * ny] = X;            // the row below segment t
-        if (t >= 1) X = add(W[((size_t)t * 4 + 2) * ny], mul(W[((size_t)t * 4 + 3) * ny], X));
+#pragma unroll
+    for (int t = PM - 2; t >= 0; --t) {
+        if (t <= P - 2) {
+            const cplx<T> Z = add(wal[t], mul(wbe[t], X));
+            LR[((size_t)(t + 1) * 2) * ny] = Z;          // the row above segment t+1
+            LR[((size_t)t * 2 + 1) * ny] = X;            // the row below segment t
+            if (t >= 1) X = add(wga[t], mul(wde[t], X));
+        }
     }
+}
+
+// the segmented march: eliminate every segment, solve the reduced systems,
+// correct and substitute (never with periodic z)
+template <typename T, int NYMAX, int NW, bool FULL>
+static hipError_t launch_seg(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
+    const dim3 block(64 * NW), grid(a.slots, batch, a.zsegs);
+    hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 3>), grid, block, 0, s, S, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t nth = (size_t)batch * a.slots * a.ny;
+    hipLaunchKernelGGL(k_zseg_reduce<T>, dim3((unsigned)((nth + 63) / 64)), dim3(64), 0, s, a, batch);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 4>), grid, block, 0, s, S, a);
+    return hipGetLastError();
 }
 
 template <typename T, int NYMAX, int NW, bool FULL>
 static hipError_t launch_pipe(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     const dim3 block(64 * NW);
-    if (a.zsegs > 0) {    // never with periodic z
-        const dim3 grid(a.slots, batch, a.zsegs);
-        hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 3>), grid, block, 0, s, S, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        const size_t nth = (size_t)batch * a.slots * a.ny;
-        hipLaunchKernelGGL(k_zseg_reduce<T>, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, a, batch);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 4>), grid, block, 0, s, S, a);
-        return hipGetLastError();
-    }
+    if (a.zsegs > 0) return launch_seg<T, NYMAX, NW, FULL>(S, a, batch, s);
     if (a.zsplit > 0) {   // never with periodic z
         const dim3 grid(a.slots, batch, 2);
         hipLaunchKernelGGL((k_zpipe<T, NYMAX, NW, FULL, false, 1>), grid, block, 0, s, S, a);
@@ -1096,6 +1117,12 @@ static hipError_t launch_mid_shape(cplx<T>* S, const MidArgs<T>& a, int batch, h
 template <typename T>
 hipError_t launch_mid(cplx<T>* S, const MidArgs<T>& a, int batch, hipStream_t s) {
     if (a.zsolver == 1 || a.zsolver == 2) return launch_mid_pcr<T>(S, a, batch, s, a.zsolver == 2);
+    // segmented lines up to 256: four wavefronts, one entry per thread, 27 KB
+    // of LDS in double, so that several segments' workgroups share a CU
+    if (a.zsegs > 0 && a.ny <= 256) {
+        if (pipe_full(a, 256, 4)) return launch_seg<T, 256, 4, true>(S, a, batch, s);
+        return launch_seg<T, 256, 4, false>(S, a, batch, s);
+    }
     // float lines of 384: one entry per thread, no idle lanes (measured 1.42 ->
     // 1.12 ms at 384^3 x 4; in double the 8-wavefront form is as fast)
     if constexpr (sizeof(T) == 4) {

@@ -95,8 +95,10 @@ def test_split_many_columns_and_adjoint():
 
 # Segmented march (three or more segments per column; plans with few columns):
 # (64, 12, 16) four whole segments, (100, 9, 6) seven with a ragged last one,
-# (61, 24, 27) four, (48, 384, 4) three in double and four in float.
-SEG_SHAPES = [(64, 12, 16), (100, 9, 6), (61, 24, 27), (48, 384, 4)]
+# (61, 24, 27) four, (48, 384, 4) three in double and four in float (the
+# march of lines up to 512), (64, 256, 8) four (the exact-count form of the
+# four-wavefront march of lines up to 256).
+SEG_SHAPES = [(64, 12, 16), (100, 9, 6), (61, 24, 27), (48, 384, 4), (64, 256, 8)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

@@ -175,10 +175,13 @@ def test_zsplit_option(lib):
         assert lib.pp_plan_set_zsplit(p, 3) == want, (nx, ny, nz, bc)
         assert lib.pp_plan_set_zsplit(p, 1) == 0 and lib.pp_plan_set_zsplit(p, 0) == 0
         lib.pp_plan_destroy(p)
-    # segments: few columns and z long enough for three of at least two chunks
-    for nx, nz, dtype, want in [(16, 48, 0, 0), (16, 33, 0, 0), (16, 32, 0, -3), (16, 48, 2, -3), (512, 4096, 0, -3)]:
-        st, p = _create(lib, nx, 8, nz, "PPPPDD", dtype=dtype)
-        assert st == 0 and lib.pp_plan_set_zsplit(p, 3) == want, (nx, nz, dtype)
+    # segments: few columns and z long enough for three of at least two
+    # chunks; y lines up to 256 aim at 1024 workgroups, longer ones at 256
+    for nx, ny, nz, dtype, want in [(16, 8, 48, 0, 0), (16, 8, 33, 0, 0), (16, 8, 32, 0, -3), (16, 8, 48, 2, -3),
+                                    (512, 8, 4096, 0, 0), (1024, 8, 4096, 0, -3),
+                                    (256, 256, 64, 0, 0), (256, 512, 64, 0, -3)]:
+        st, p = _create(lib, nx, ny, nz, "PPPPDD", dtype=dtype)
+        assert st == 0 and lib.pp_plan_set_zsplit(p, 3) == want, (nx, ny, nz, dtype)
         lib.pp_plan_destroy(p)
 
 
