@@ -144,12 +144,15 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
  *                   segments;
  *   PP_ZSPLIT_OFF   always one workgroup per column;
  *   PP_ZSPLIT_ON    always split in two (two workgroups per column);
- *   PP_ZSPLIT_SEG   always segmented: each column in 3 to 16 segments (enough
- *                   for about 256 workgroups), each eliminated on its own,
- *                   their end rows coupled through a small reduced system
- *                   solved between two launches (f64 and f32 plans whose
- *                   columns number at most 85 and whose nz holds three
- *                   segments of at least two chunks).
+ *   PP_ZSPLIT_SEG   always segmented: each column in 3 to 16 segments, each
+ *                   eliminated on its own, their end rows coupled through a
+ *                   small reduced system solved between two launches.
+ *                   Segments enough for about 256 workgroups on y lines over
+ *                   256, 768 (PP_F64) or 1024 (PP_F32) on lines up to 256;
+ *                   the form exists for f64 and f32 plans where that means
+ *                   three segments or more (columns at most 85 on lines over
+ *                   256; 256 in f64, 341 in f32 on lines up to 256) and nz
+ *                   holds three segments of at least two chunks.
  * The split form exists for non-periodic z, y lines up to 1024 and nz of at
  * least two chunks of the march (16 planes; 12 for float lines of 384, 8 for
  * double lines over 512): PP_ZSPLIT_ON / PP_ZSPLIT_SEG on other shapes return
