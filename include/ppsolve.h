@@ -132,7 +132,12 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
 /* Layout of the Thomas march (PP_ZSOLVER_THOMAS; the other solvers ignore it).
  *   PP_ZSPLIT_AUTO  default: split where the columns (x-wavenumber slots times
  *                   batch) are at most 1/2 (PP_F64), 2 (PP_F32) or 4
- *                   (PP_F32_REFINED) per compute unit of the device, and
+ *                   (PP_F32_REFINED) per compute unit of the device, or, in
+ *                   PP_F64 on y lines up to 512 with more columns than
+ *                   compute units, where the split's rounds of workgroups
+ *                   (two launches of ceil(2 columns / CUs), each about a
+ *                   quarter of a column's march) take less than the whole
+ *                   march's ceil(columns / CUs); and
  *                   segmented where the plan has segments (below), provided
  *                   no z-system is so close to singular that splitting it
  *                   amplifies rounding by more than 256 (the zero mode and

@@ -890,13 +890,23 @@ pp::MidArgs<T> make_midargs(pp_plan p, unsigned char* ws, bool project, bool dem
     // units or more without a workgroup
     // automatic, by columns (slots x batch) per compute unit, as measured:
     // double at most 1/2 (one workgroup per CU either way: 256^3 with 128
-    // columns 0.31 -> 0.18 ms; 193 or 256 columns 2-5% slower split); float at
+    // columns 0.31 -> 0.18 ms; 192 or 256 columns 2-5% slower split); float at
     // most 2 (the halves run two per CU: 512^3 0.53 -> 0.44 ms, 1024^2 x 512
-    // 2.50 -> 2.36 ms; 772 columns 11% slower); the refined solve's mixed
-    // march at most 4 (772 columns of 384^3 x 4: 1.61 -> 1.30 ms)
+    // 2.50 -> 2.36 ms; 768 columns 11% slower); the refined solve's mixed
+    // march at most 4 (768 columns of 384^3 x 4: 1.61 -> 1.30 ms).
+    // Double on lines up to 512, beyond one column per CU: each workgroup's
+    // march is latency-bound, so the whole march takes ceil(c / CUs) rounds
+    // of one column's time T however full its last round is, and the split
+    // two launches of ceil(2c / CUs) rounds of about 0.26 T; split where
+    // that is shorter (384^3 DD DD DD: 576 columns 2.02 -> 1.75 ms, 1152
+    // 3.37 -> 3.05; 768 and 960 columns whole, 2.05 and 2.71 ms)
     a.zsplit = 0;
     const long long cols = (long long)p->slots * p->batch, cus = pp::device_cus();
-    const long long lim = p->dtype == PP_F64 ? cus / 2 : (p->dtype == PP_F32 ? 2 * cus : 4 * cus);
+    long long lim = p->dtype == PP_F64 ? cus / 2 : (p->dtype == PP_F32 ? 2 * cus : 4 * cus);
+    if (p->dtype == PP_F64 && p->ny <= 512 && cols > cus) {
+        const long long whole = (cols + cus - 1) / cus, halves = (2 * cols + cus - 1) / cus;
+        if (13 * halves < 25 * whole) lim = cols;
+    }
     // the amplification bound holds double plans to the single march's
     // accuracy; float rounding (6e-8) dominates the two-way split's meeting
     // rows (512^3 periodic x, y: 1.97e-6 split, 1.81e-6 whole, from the f64
