@@ -137,8 +137,8 @@ pp_status pp_plan_set_zsolver(pp_plan p, pp_zsolver solver);
  *                   compute units, where the split's rounds of workgroups
  *                   (two launches of ceil(2 columns / CUs), each about a
  *                   quarter of a column's march) take less than the whole
- *                   march's ceil(columns / CUs); and
- *                   segmented where the plan has segments (below), provided
+ *                   march's ceil(columns / CUs); and, in place of either,
+ *                   segmented wherever the plan has segments (below), provided
  *                   no z-system is so close to singular that splitting it
  *                   amplifies rounding by more than 256 (the zero mode and
  *                   lowest wavenumbers of long columns under Neumann or
