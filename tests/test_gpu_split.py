@@ -179,3 +179,19 @@ def test_auto_keeps_near_singular_columns_whole():
     assert np.array_equal(u32, u32_on)
     assert rel_max(u32, oracle.solve(f32, bc, h, "mean")) < 1e-5
 
+
+
+def test_auto_segments_where_columns_alone_would_not_split():
+    """Double lines up to 256 with 129-256 columns: the automatic layout takes
+    the plan's segments (same kernels as the forced segmented march, so the
+    same bits) and meets the 1e-12 bar."""
+    from gpu_util import banner, rel_max
+    rng = np.random.default_rng(27)
+    shape, bc = (64, 16, 384), "DDNNNN"
+    h = (1.0 / 384, 1.0 / 16, 1.0 / 64)
+    f = rng.standard_normal(shape)
+    banner(f"auto segments {shape}")
+    u, _ = _solve(f, bc, h, "f64", "auto")
+    us, _ = _solve(f, bc, h, "f64", "seg")
+    assert np.array_equal(u, us)
+    assert rel_max(u, oracle.solve(f, bc, h, "mean")) < 1e-12
